@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the probed FWI gradient on one MI355X.
+
+One step = one complete probed-gradient call (probe generation, forward
+propagation with on-the-fly probing, residual and objective, adjoint
+propagation with on-the-fly probing, imaging) over the whole shot batch, with
+every input already resident in HBM.
+
+Metric: GPts/s = shots * padded grid points * 2 (nt - 1) / wall time, the
+grid-point updates of the forward and adjoint passes.  The JSON line also
+carries the roofline of the dominant kernel (the leapfrog step), the p50/p99
+latency of the gradient call, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c1_layered_2d_16shots")
+    ap.add_argument("--r", type=int, default=None, help="probes (default: the workload's)")
+    ap.add_argument("--probe", default=None, help="rademacher | gauss_b64")
+    ap.add_argument("--block", type=int, default=0, help="time steps per probe contraction (0 = default)")
+    ap.add_argument("--keep-vbar", action="store_true", help="accumulate vbar instead of folding it")
+    ap.add_argument("--nt", type=int, default=None, help="override the record length (profiling runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-nt", type=int, default=0, help="time steps of the CPU-oracle sample (0 = full record)")
+    ap.add_argument("--no-profile-pass", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the whole gradient of a shot batch on a single "
+              "MI355X and has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_00794_amd import build as tbuild
+    if not os.path.exists(tbuild.LIB_PATH):
+        tbuild.build(force=True)
+    from paper_2104_00794_amd import tpx
+    from paper_2104_00794_amd.inputs import workload
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    wl = workload(args.workload)
+    if args.nt:
+        wl = wl.with_(nt=args.nt)
+    r = args.r or wl.r
+    kind = args.probe or wl.probe
+    mt, m0 = wl.models()
+    grid = tpx.Grid(wl.shape, h=wl.h, dt=wl.dt, nt=wl.nt, order=wl.order, nbl=wl.nbl, damp_vmax=wl.vmax,
+                    damp_R=wl.damp_R)
+    wav = torch.tensor(wl.wavelet(), dtype=torch.float32, device=dev)
+    geom = tpx.Geometry(wl.src_pos(), wl.rec_pos(), wav)
+    m_true = torch.tensor(mt, dtype=torch.float32, device=dev)
+    m_0 = torch.tensor(m0, dtype=torch.float32, device=dev)
+    probe = tpx.Probe(kind=kind, r=r, seed=wl.probe_seed, block=args.block, keep_vbar=args.keep_vbar)
+
+    d_obs = tpx.forward(grid, geom, m_true)           # synthetic observed data (untimed input)
+    ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_PROBED, grid, geom, probe, dev)
+    g = torch.empty(tuple(wl.shape), dtype=torch.float32, device=dev)
+    J = torch.empty(1, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        tpx.gradient_probed(grid, geom, probe, m_0, d_obs, ws=ws, g_out=g, J_out=J, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    tpx.check_workspace(ws)
+
+    # ---- timed region: K complete gradient calls ------------------------------------------
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+
+    S, npad, nphys, nt = wl.nshots, wl.n_pad, wl.n_phys, wl.nt
+    updates = S * npad * 2 * (nt - 1)
+    gpts = updates / (ms_per_step * 1e-3) / 1e9
+    phi = nphys / npad
+    b_alg_path = 12.0 + 4.0 / S + 4.0 * phi        # bytes per shot-point-step of the whole path
+    b_alg_step = 12.0 + 4.0 / S                     # leapfrog step kernel alone
+
+    # ---- per-kernel durations (HIP events on the launch stream) ----------------------------
+    kernels = {}
+    roofline = None
+    if not args.no_profile_pass:
+        tpx.profile_enable(True)
+        step()
+        torch.cuda.synchronize()
+        for name, kid in (("step", tpx.KERNEL_STEP), ("accum_fwd", tpx.KERNEL_ACCUM_FWD),
+                          ("accum_adj", tpx.KERNEL_ACCUM_ADJ)):
+            tot, n = tpx.profile_read(kid)
+            kernels[name] = {"total_ms": round(tot, 4), "launches": n,
+                             "avg_us": round(1e3 * tot / n, 3) if n else None}
+        tpx.profile_enable(False)
+        st = kernels["step"]
+        if st["launches"]:
+            bytes_per_launch = S * npad * 12.0 + npad * 4.0
+            achieved = bytes_per_launch / (st["avg_us"] * 1e-6) / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "k_step2d<R=%d>" % (wl.order // 2) if wl.ndim == 2 else
+                        "k_step3d<R=%d>" % (wl.order // 2),
+                        "bytes_per_launch": bytes_per_launch, "avg_launch_us": st["avg_us"]}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, r, kind, args.cpu_nt or wl.nt)
+
+    out = {
+        "metric": "GPts/s fwd+adj with r-probe accumulation (%HBM roofline); gradient p50/p99 latency",
+        "value": round(gpts, 3),
+        "unit": "GPts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "grid": "x".join(str(s) for s in wl.shape[::-1]), "h_m": wl.h,
+                   "space_order": wl.order, "shots": S, "nt": nt, "nbl": wl.nbl, "r": r, "probe": kind,
+                   "block": args.block or "default", "keep_vbar": bool(args.keep_vbar),
+                   "padded_points_per_shot": npad, "parallelism": "single-gpu"},
+        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                       "p99": round(float(np.percentile(lat, 99)), 3)},
+        "hbm_roofline_pct": round(100.0 * gpts * b_alg_path / HBM_PEAK_GBS, 2),
+        "b_alg_bytes_per_point_step": round(b_alg_path, 3),
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+        "J": float(J.item()),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, r, kind, nt_sample):
+    """FP64 oracle, one shot of the workload, first nt_sample time steps."""
+    import oracle
+    oracle.build(force=False)
+    sample = wl.with_(nt=nt_sample, src=[wl.src[0]])
+    mt, m0 = sample.models()
+    og = oracle.Grid(sample.shape, h=sample.h, dt=sample.dt, nt=sample.nt, order=sample.order, nbl=sample.nbl,
+                     damp_vmax=sample.vmax, damp_R=sample.damp_R)
+    dobs = np.zeros((1, sample.nt, len(sample.rec)))
+    t0 = time.perf_counter()
+    oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind=kind, r=r,
+                           seed=sample.probe_seed)
+    dt = time.perf_counter() - t0
+    upd = sample.n_pad * 2 * (sample.nt - 1)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(upd / dt / 1e9, 5), "unit": "GPts/s", "cores": cores, "kind": "oracle",
+            "seconds": round(dt, 2),
+            "sample": "1 of %d shots, first %d of %d time steps, r=%d %s, same grid; FP64 C oracle with OpenMP"
+                      % (wl.nshots, sample.nt, wl.nt, r, kind)}
+
+
+if __name__ == "__main__":
+    main()

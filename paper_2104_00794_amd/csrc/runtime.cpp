@@ -1,0 +1,880 @@
+// Host runtime of the tpx library: argument validation, the workspace plan,
+// geometry tables (interpolation weights and per-tile injection lists), and
+// the time-loop drivers behind the C-ABI of include/tpx.h.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "tpx.h"
+#include "tpx_internal.h"
+
+using namespace tpx;
+
+namespace {
+
+thread_local std::string g_err;
+
+tpx_status fail(tpx_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define TPX_HIP(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(TPX_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// ---------------------------------------------------------------------------
+// optional per-launch timing with HIP events on the launch stream
+// ---------------------------------------------------------------------------
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<ProfRec> recs;
+};
+
+Profiler &profiler() {
+    static Profiler p;
+    return p;
+}
+
+hipEvent_t take_event(Profiler &p) {
+    if (p.used == p.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p.pool.push_back(e);
+    }
+    return p.pool[p.used++];
+}
+
+template <class F>
+hipError_t prof(int kind, hipStream_t s, F &&launch) {
+    Profiler &p = profiler();
+    if (!p.on) return launch();
+    std::lock_guard<std::mutex> lk(p.mu);
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return launch();
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e == hipSuccess) p.recs.push_back({kind, a, b});
+    return e;
+}
+
+// Sum of |weights| of the centred second-difference stencil (Taylor
+// coefficients): bounds the spectral radius of the discrete Laplacian.
+double stencil_abs_sum(int order) { return order == 4 ? 16.0 / 3.0 : 6.501587301587302; }
+
+// Centred second-derivative weights (Taylor expansion): centre, then distance 1..R.
+void stencil_weights(int order, double c[5]) {
+    for (int i = 0; i < 5; ++i) c[i] = 0.0;
+    if (order == 4) {
+        c[0] = -2.5;
+        c[1] = 4.0 / 3.0;
+        c[2] = -1.0 / 12.0;
+    } else {
+        c[0] = -205.0 / 72.0;
+        c[1] = 1.6;
+        c[2] = -0.2;
+        c[3] = 8.0 / 315.0;
+        c[4] = -1.0 / 560.0;
+    }
+}
+
+struct Problem {
+    Layout L;
+    Physics ph;
+    int nt;
+    double dt;
+    int nrec;
+};
+
+tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
+    if (!g || !geo) return fail(TPX_E_INVAL, "grid and geometry must not be NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(TPX_E_INVAL, "ndim must be 2 or 3");
+    if (g->space_order != 4 && g->space_order != 8) return fail(TPX_E_INVAL, "space_order must be 4 or 8");
+    if (g->n[0] < 2 || g->n[2] < 2 || (g->ndim == 3 && g->n[1] < 2) || (g->ndim == 2 && g->n[1] != 1))
+        return fail(TPX_E_INVAL, "grid sizes: n[0], n[2] >= 2; n[1] >= 2 in 3D and == 1 in 2D");
+    if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(TPX_E_INVAL, "h must be positive");
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(TPX_E_INVAL, "dt must be positive");
+    if (g->nt < 2) return fail(TPX_E_INVAL, "nt must be >= 2");
+    if (g->nbl < 0) return fail(TPX_E_INVAL, "nbl must be >= 0");
+    if (!(g->damp_vmax > 0.0)) return fail(TPX_E_INVAL, "damp_vmax must be positive");
+    if (!(g->damp_R > 0.0 && g->damp_R <= 1.0)) return fail(TPX_E_INVAL, "damp_R must be in (0, 1]");
+    if (geo->nshots < 1 || geo->nrec < 0) return fail(TPX_E_INVAL, "nshots >= 1 and nrec >= 0 required");
+    if (!geo->src_pos || (geo->nrec > 0 && !geo->rec_pos))
+        return fail(TPX_E_INVAL, "source/receiver positions must not be NULL");
+    // leapfrog stability: dt <= 2 h / (vmax sqrt(D sum|c|))
+    const double limit = 2.0 * g->h / (g->damp_vmax * std::sqrt((double)g->ndim * stencil_abs_sum(g->space_order)));
+    if (g->dt > limit * (1.0 + 1e-12)) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "dt = %g ms exceeds the stability limit %g ms for vmax = %g km/s", g->dt, limit,
+                 g->damp_vmax);
+        return fail(TPX_E_CFL, buf);
+    }
+
+    Layout &L = P->L;
+    L.ndim = g->ndim;
+    L.R = g->space_order / 2;
+    L.nb = g->nbl;
+    L.S = geo->nshots;
+    for (int a = 0; a < 3; ++a) L.n[a] = g->n[a];
+    L.P[0] = L.n[0] + 2 * L.nb;
+    L.P[1] = L.ndim == 3 ? L.n[1] + 2 * L.nb : 1;
+    L.P[2] = L.n[2] + 2 * L.nb;
+    const int64_t need0 = XO + L.P[0] + L.R;
+    L.G[0] = (need0 + 31) / 32 * 32;
+    L.G[1] = L.ndim == 3 ? L.P[1] + 2 * L.R : 1;
+    L.G[2] = L.P[2] + 2 * L.R;
+    L.oy = L.ndim == 3 ? L.R : 0;
+    L.shot_floats = L.G[0] * L.G[1] * L.G[2];
+    L.slot_floats = L.shot_floats * L.S;
+    L.nphys = L.n[0] * L.n[1] * L.n[2];
+    L.npad = L.P[0] * L.P[1] * L.P[2];
+    if (L.shot_floats >= (int64_t)1 << 31) return fail(TPX_E_INVAL, "one shot's field exceeds 2^31 floats");
+    if (L.ndim == 2) {
+        L.tile[0] = T2X; L.tile[1] = 1; L.tile[2] = T2Z;
+    } else {
+        L.tile[0] = T3X; L.tile[1] = T3Y; L.tile[2] = 1;
+    }
+    for (int a = 0; a < 3; ++a) L.ntiles[a] = (L.P[a] + L.tile[a] - 1) / L.tile[a];
+    L.tiles_per_shot = L.ntiles[0] * L.ntiles[1] * L.ntiles[2];
+
+    double c[5];
+    stencil_weights(g->space_order, c);
+    const double ih2 = 1.0 / (g->h * g->h);
+    for (int i = 0; i < 5; ++i) P->ph.c[i] = (float)(c[i] * ih2);
+    const double dmax = L.nb > 0 ? 3.0 * g->damp_vmax / (2.0 * L.nb * g->h) * std::log(1.0 / g->damp_R) : 0.0;
+    P->ph.hd_max = (float)(0.5 * dmax * g->dt);
+    P->ph.inv_nb = L.nb > 0 ? (float)(1.0 / L.nb) : 0.0f;
+    P->nt = g->nt;
+    P->dt = g->dt;
+    P->nrec = geo->nrec;
+    return TPX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// geometry tables
+// ---------------------------------------------------------------------------
+
+struct Corners {
+    int cnt;
+    int64_t ix[8], iy[8], iz[8];  // padded coordinates
+    double w[8];
+};
+
+// Bilinear / trilinear weights: base node i0 = min(floor(x/h), n-2),
+// fraction x/h - i0; order of corners: z, then y, then x (x fastest).
+bool corners_of(const Problem &P, const tpx_grid *g, const double pos[3], Corners *c) {
+    const Layout &L = P.L;
+    int64_t i0[3] = {0, 0, 0};
+    double f[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) {
+        if (L.ndim == 2 && a == 1) continue;
+        const double x = pos[a] / g->h;
+        if (!(x >= 0.0) || x > (double)(L.n[a] - 1) * (1.0 + 1e-12)) return false;
+        int64_t b = (int64_t)std::floor(x);
+        if (b > L.n[a] - 2) b = L.n[a] - 2;
+        i0[a] = b;
+        f[a] = x - (double)b;
+    }
+    const int ny = L.ndim == 3 ? 2 : 1;
+    const int64_t oyb = L.ndim == 3 ? L.nb : 0;
+    c->cnt = 0;
+    for (int dz = 0; dz < 2; ++dz)
+        for (int dy = 0; dy < ny; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                double w = (dx ? f[0] : 1.0 - f[0]) * (dz ? f[2] : 1.0 - f[2]);
+                if (L.ndim == 3) w *= (dy ? f[1] : 1.0 - f[1]);
+                const int i = c->cnt++;
+                c->ix[i] = i0[0] + dx + L.nb;
+                c->iy[i] = i0[1] + dy + oyb;
+                c->iz[i] = i0[2] + dz + L.nb;
+                c->w[i] = w;
+            }
+    return true;
+}
+
+// Upper bounds used to size the table area independently of positions.
+struct TableCaps {
+    int64_t src_ent, rec_ent, tile_ptr, smp_rec, smp_src, nc;
+};
+
+TableCaps table_caps(const Problem &P) {
+    TableCaps t;
+    t.nc = P.L.ndim == 3 ? 8 : 4;
+    t.src_ent = (int64_t)P.L.S * t.nc;
+    t.rec_ent = (int64_t)P.L.S * P.nrec * t.nc;
+    t.tile_ptr = (int64_t)P.L.S * P.L.tiles_per_shot + 1;
+    t.smp_rec = (int64_t)P.L.S * P.nrec;
+    t.smp_src = P.L.S;
+    return t;
+}
+
+struct Blob {
+    std::vector<unsigned char> bytes;
+    size_t put(const void *p, size_t n) {
+        const size_t off = bytes.size();
+        bytes.resize(align_up(off + n));
+        if (n) memcpy(bytes.data() + off, p, n);
+        return off;
+    }
+};
+
+size_t inject_bytes(int64_t tile_ptr, int64_t ent) {
+    return align_up(tile_ptr * 4) + 3 * align_up(ent * 4) + align_up((ent + 1) * 4) + align_up(ent * 4);
+}
+size_t sample_bytes(int64_t n, int64_t nc) { return align_up(n * 4) + align_up(n * nc * 4); }
+
+size_t tables_bytes(const Problem &P) {
+    const TableCaps t = table_caps(P);
+    return inject_bytes(t.tile_ptr, t.src_ent) + inject_bytes(t.tile_ptr, t.rec_ent) + sample_bytes(t.smp_rec, t.nc) +
+           sample_bytes(t.smp_src, t.nc);
+}
+
+struct HostInject {  // offsets into the blob
+    size_t tile_ptr, seg_local, seg_ent, ent_idx, ent_w;
+};
+struct HostSample {
+    size_t base, w;
+    int32_t n;
+};
+
+struct Entry {
+    int64_t tile;
+    int32_t local;
+    int32_t idx;
+    float w;
+};
+
+HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
+    const Layout &L = P.L;
+    std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &c) {
+        if (a.tile != c.tile) return a.tile < c.tile;
+        if (a.local != c.local) return a.local < c.local;
+        return a.idx < c.idx;
+    });
+    const int64_t ntile = (int64_t)L.S * L.tiles_per_shot;
+    std::vector<int32_t> tile_ptr(ntile + 1, 0), seg_local, seg_ent, ent_idx;
+    std::vector<float> ent_w;
+    for (size_t i = 0; i < ent.size(); ++i) {
+        const bool new_seg = i == 0 || ent[i].tile != ent[i - 1].tile || ent[i].local != ent[i - 1].local;
+        if (new_seg) {
+            seg_local.push_back(ent[i].local);
+            seg_ent.push_back((int32_t)i);
+            tile_ptr[ent[i].tile + 1]++;
+        }
+        ent_idx.push_back(ent[i].idx);
+        ent_w.push_back(ent[i].w);
+    }
+    seg_ent.push_back((int32_t)ent.size());
+    for (int64_t t = 0; t < ntile; ++t) tile_ptr[t + 1] += tile_ptr[t];
+    HostInject h;
+    h.tile_ptr = b.put(tile_ptr.data(), tile_ptr.size() * 4);
+    h.seg_local = b.put(seg_local.data(), seg_local.size() * 4);
+    h.seg_ent = b.put(seg_ent.data(), seg_ent.size() * 4);
+    h.ent_idx = b.put(ent_idx.data(), ent_idx.size() * 4);
+    h.ent_w = b.put(ent_w.data(), ent_w.size() * 4);
+    return h;
+}
+
+void push_corners(const Problem &P, const Corners &c, int shot, int idx, std::vector<Entry> &ent) {
+    const Layout &L = P.L;
+    for (int i = 0; i < c.cnt; ++i) {
+        if (c.w[i] == 0.0) continue;  // contributes exactly nothing
+        const int64_t tx = c.ix[i] / L.tile[0], ty = c.iy[i] / L.tile[1], tz = c.iz[i] / L.tile[2];
+        Entry e;
+        e.tile = (((int64_t)shot * L.ntiles[2] + tz) * L.ntiles[1] + ty) * L.ntiles[0] + tx;
+        e.local = (int32_t)((((c.iz[i] % L.tile[2]) * L.tile[1]) + (c.iy[i] % L.tile[1])) * L.tile[0] +
+                            (c.ix[i] % L.tile[0]));
+        e.idx = idx;
+        e.w = (float)c.w[i];
+        ent.push_back(e);
+    }
+}
+
+HostSample add_sample(Blob &b, const Problem &P, const std::vector<Corners> &cs) {
+    const int nc = P.L.ndim == 3 ? 8 : 4;
+    std::vector<int32_t> base(cs.size());
+    std::vector<float> w(cs.size() * nc);
+    for (size_t i = 0; i < cs.size(); ++i) {
+        base[i] = (int32_t)P.L.pad_off(cs[i].ix[0], cs[i].iy[0], cs[i].iz[0]);
+        for (int j = 0; j < nc; ++j) w[i * nc + j] = (float)cs[i].w[j];
+    }
+    HostSample h;
+    h.base = b.put(base.data(), base.size() * 4);
+    h.w = b.put(w.data(), w.size() * 4);
+    return h;
+}
+
+struct Tables {
+    Blob blob;
+    HostInject src_inj, rec_inj;
+    HostSample rec_smp, src_smp;
+};
+
+tpx_status build_tables(const Problem &P, const tpx_grid *g, const tpx_geom *geo, Tables *T) {
+    const int S = P.L.S;
+    std::vector<Corners> src(S), rec((size_t)S * P.nrec);
+    for (int s = 0; s < S; ++s) {
+        if (!corners_of(P, g, &geo->src_pos[3 * s], &src[s])) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "source of shot %d lies outside the physical grid", s);
+            return fail(TPX_E_GEOM, buf);
+        }
+        for (int i = 0; i < P.nrec; ++i)
+            if (!corners_of(P, g, &geo->rec_pos[3 * ((int64_t)s * P.nrec + i)], &rec[(size_t)s * P.nrec + i])) {
+                char buf[128];
+                snprintf(buf, sizeof buf, "receiver %d of shot %d lies outside the physical grid", i, s);
+                return fail(TPX_E_GEOM, buf);
+            }
+    }
+    std::vector<Entry> es, er;
+    for (int s = 0; s < S; ++s) push_corners(P, src[s], s, 0, es);
+    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < P.nrec; ++i) push_corners(P, rec[(size_t)s * P.nrec + i], s, i, er);
+    T->src_inj = add_inject(T->blob, P, es);
+    T->rec_inj = add_inject(T->blob, P, er);
+    T->rec_smp = add_sample(T->blob, P, rec);
+    T->rec_smp.n = P.nrec;
+    T->src_smp = add_sample(T->blob, P, src);
+    T->src_smp.n = 1;
+    return TPX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace plan
+// ---------------------------------------------------------------------------
+
+int default_block(int r, int nt) {
+    int b = r <= 16 ? 32 : 64;
+    if (b > nt - 1) b = nt - 1;
+    if (b < 1) b = 1;
+    return b;
+}
+
+struct Plan {
+    size_t flags, parts, J, beta, ring, hist, Z, ubar, vbar, gpart, res, d, tables, total;
+    int nslots, block;
+};
+
+enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED };
+
+tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
+    if (!pr) return fail(TPX_E_INVAL, "probe must not be NULL for probed calls");
+    if (pr->r < 1) return fail(TPX_E_INVAL, "r must be >= 1");
+    if (pr->kind < 0 || pr->kind > 3) return fail(TPX_E_INVAL, "unknown probe kind");
+    if (pr->kind == TPX_PROBE_IDENTITY && pr->r != P.nt) return fail(TPX_E_INVAL, "identity probes need r == nt");
+    if (pr->kind == TPX_PROBE_EXPLICIT && !pr->Z) return fail(TPX_E_INVAL, "explicit probes need Z");
+    if (pr->block < 0) return fail(TPX_E_INVAL, "block must be >= 0");
+    return TPX_OK;
+}
+
+Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr) {
+    const Layout &L = P.L;
+    Plan p;
+    memset(&p, 0, sizeof p);
+    const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
+    const int r = probed ? pr->r : 0;
+    p.block = default_block(r, P.nt);
+    if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
+    if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
+    p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? 3 : p.block + 2;
+    const size_t slot = (size_t)L.slot_floats * 4;
+    const size_t ntr = (size_t)L.S * P.nt * P.nrec;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align_up(bytes);
+        return at;
+    };
+    p.flags = take(64);
+    p.parts = take(512 * 8);
+    p.J = take(8);
+    p.beta = take((size_t)L.shot_floats * 4);
+    p.ring = take(slot * p.nslots);
+    if (mode == M_GRAD_FULL) p.hist = take(slot * (size_t)P.nt);
+    if (probed && pr->kind != TPX_PROBE_EXPLICIT) p.Z = take((size_t)L.S * P.nt * r * 4);
+    if (mode == M_GRAD_PROBED) p.ubar = take((size_t)L.S * r * L.nphys * 4);
+    const bool keep_v = probed && pr->keep_vbar;
+    if ((mode == M_GRAD_PROBED || mode == M_BWD_PROBED) && keep_v) p.vbar = take((size_t)L.S * r * L.nphys * 4);
+    if (mode == M_GRAD_FULL || ((mode == M_GRAD_PROBED || mode == M_BWD_PROBED) && !keep_v))
+        p.gpart = take((size_t)L.S * L.nphys * 4);
+    if (mode == M_GRAD_PROBED || mode == M_GRAD_FULL) {
+        p.res = take(ntr * 4);
+        p.d = take(ntr * 4);
+    }
+    p.tables = take(tables_bytes(P));
+    p.total = o;
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// drivers
+// ---------------------------------------------------------------------------
+
+struct Ctx {
+    Problem P;
+    Plan plan;
+    unsigned char *ws;
+    hipStream_t stream;
+    InjectTables src_inj, rec_inj;
+    SampleTables rec_smp, src_smp;  // out/scales filled per use
+    float *beta;
+    float *ring;
+};
+
+InjectTables dev_inject(unsigned char *base, const HostInject &h) {
+    InjectTables t;
+    t.tile_ptr = (const int32_t *)(base + h.tile_ptr);
+    t.seg_local = (const int32_t *)(base + h.seg_local);
+    t.seg_ent = (const int32_t *)(base + h.seg_ent);
+    t.ent_idx = (const int32_t *)(base + h.ent_idx);
+    t.ent_w = (const float *)(base + h.ent_w);
+    return t;
+}
+
+SampleTables dev_sample(unsigned char *base, const HostSample &h) {
+    SampleTables t;
+    memset(&t, 0, sizeof t);
+    t.nsmp = h.n;
+    t.base = (const int32_t *)(base + h.base);
+    t.w = (const float *)(base + h.w);
+    return t;
+}
+
+tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe *pr, Mode mode, const float *m,
+                 void *ws, size_t ws_bytes, void *stream) {
+    tpx_status st = make_problem(g, geo, &C.P);
+    if (st != TPX_OK) return st;
+    const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
+    if (probed) {
+        st = check_probe(C.P, pr);
+        if (st != TPX_OK) return st;
+    }
+    if (!m) return fail(TPX_E_INVAL, "model m must not be NULL");
+    if (!geo->wavelet && (mode != M_ADJOINT && mode != M_BWD_PROBED))
+        return fail(TPX_E_INVAL, "wavelet must not be NULL");
+    C.plan = make_plan(C.P, mode, pr);
+    if (!ws || ws_bytes < C.plan.total) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes,
+                 C.plan.total);
+        return fail(TPX_E_NOMEM, buf);
+    }
+    Tables T;
+    st = build_tables(C.P, g, geo, &T);
+    if (st != TPX_OK) return st;
+    if (T.blob.bytes.size() > tables_bytes(C.P)) return fail(TPX_E_INVAL, "internal: geometry tables overflow");
+    C.ws = (unsigned char *)ws;
+    C.stream = (hipStream_t)stream;
+    unsigned char *tb = C.ws + C.plan.tables;
+    if (!T.blob.bytes.empty()) {
+        TPX_HIP(hipMemcpyAsync(tb, T.blob.bytes.data(), T.blob.bytes.size(), hipMemcpyHostToDevice, C.stream));
+        TPX_HIP(hipStreamSynchronize(C.stream));  // the host blob is released on return
+    }
+    C.src_inj = dev_inject(tb, T.src_inj);
+    C.rec_inj = dev_inject(tb, T.rec_inj);
+    C.rec_smp = dev_sample(tb, T.rec_smp);
+    C.src_smp = dev_sample(tb, T.src_smp);
+    C.beta = (float *)(C.ws + C.plan.beta);
+    C.ring = (float *)(C.ws + C.plan.ring);
+    TPX_HIP(launch_fill_zero(C.ws + C.plan.flags, kAlign, C.stream));
+    const float m_min = (float)(1.0 / (g->damp_vmax * g->damp_vmax) * (1.0 - 1e-5));
+    TPX_HIP(launch_model_prep(C.P.L, m, C.P.dt, m_min, C.beta, (int32_t *)(C.ws + C.plan.flags), C.stream));
+    return TPX_OK;
+}
+
+float *slot_ptr(float *base, const Layout &L, int nslots, int k) {
+    const int s = ((k % nslots) + nslots) % nslots;
+    return base + (int64_t)s * L.slot_floats;
+}
+
+// Forward propagation over k = 0..nt-2 in the ring (or the history when
+// `hist` is set), sampling traces into d.  When `Z` is set, the probed
+// wavefield ubar_j += Z[s,j] u^s is accumulated every `block` steps.
+tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, const float *Z, int r, float *ubar) {
+    const Layout &L = C.P.L;
+    const int nt = C.P.nt;
+    float *buf = hist ? hist : C.ring;
+    const int ns = hist ? nt : C.plan.nslots;
+    TPX_HIP(launch_fill_zero(hist ? (void *)hist : (void *)C.ring, (size_t)L.slot_floats * 4 * ns, C.stream));
+    if (ubar) TPX_HIP(launch_fill_zero(ubar, align_up((size_t)L.S * r * L.nphys * 4), C.stream));
+    StepArgs a;
+    memset(&a, 0, sizeof a);
+    a.beta = C.beta;
+    a.inject = 1;
+    a.inj = C.src_inj;
+    a.amp.ptr = wavelet;
+    a.amp.shot_stride = nt;
+    a.amp.k_stride = 1;
+    a.amp.scale = 1.0f;
+    SampleTables smp = C.rec_smp;
+    smp.out = d;
+    smp.out_shot_stride = (int64_t)nt * C.P.nrec;
+    smp.out_k_stride = C.P.nrec;
+    smp.scale = 1.0f;
+    a.do_sample = (d && smp.nsmp > 0) ? 1 : 0;
+    a.smp = smp;
+    int s_lo = 1;
+    for (int k = 0; k <= nt - 2; ++k) {
+        a.k = k;
+        a.cur = slot_ptr(buf, L, ns, k);
+        a.prev = k == 0 ? a.cur : slot_ptr(buf, L, ns, k - 1);  // u^{-1} = u^0 = 0
+        a.next = slot_ptr(buf, L, ns, k + 1);
+        TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
+        const int s = k + 1;
+        if (Z && (s - s_lo + 1 == C.plan.block || s == nt - 1)) {
+            TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream,
+                         [&] { return launch_accum_fwd(L, buf, ns, s_lo, s, Z, nt, r, ubar, C.stream); }));
+            s_lo = s + 1;
+        }
+    }
+    if (a.do_sample) TPX_HIP(launch_sample_only(L, slot_ptr(buf, L, ns, nt - 1), nt - 1, smp, C.stream));
+    return TPX_OK;
+}
+
+// Adjoint propagation k = nt-1..1 injecting amp/dt^2 at the receivers.
+// Optional: q_adj sampling at the source (scale dt^2), probe accumulation
+// (fold into gpart or into vbar), or the full-history imaging term.
+struct AdjOut {
+    float *q_adj = nullptr;
+    const float *Z = nullptr;
+    int r = 0;
+    int fold = 1;
+    const float *ubar = nullptr;
+    float c = 1.0f;
+    float *vbar = nullptr;
+    float *gpart = nullptr;
+    const float *hist = nullptr;
+};
+
+tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
+    const Layout &L = C.P.L;
+    const int nt = C.P.nt;
+    const int ns = C.plan.nslots;
+    TPX_HIP(launch_fill_zero(C.ring, (size_t)L.slot_floats * 4 * ns, C.stream));
+    if (o.gpart) TPX_HIP(launch_fill_zero(o.gpart, align_up((size_t)L.S * L.nphys * 4), C.stream));
+    if (o.vbar) TPX_HIP(launch_fill_zero(o.vbar, align_up((size_t)L.S * o.r * L.nphys * 4), C.stream));
+    StepArgs a;
+    memset(&a, 0, sizeof a);
+    a.beta = C.beta;
+    a.inject = C.P.nrec > 0 ? 1 : 0;
+    a.inj = C.rec_inj;
+    a.amp.ptr = amp;
+    a.amp.shot_stride = (int64_t)nt * C.P.nrec;
+    a.amp.k_stride = C.P.nrec;
+    a.amp.scale = (float)(1.0 / (C.P.dt * C.P.dt));
+    SampleTables smp = C.src_smp;
+    smp.out = o.q_adj;
+    smp.out_shot_stride = nt;
+    smp.out_k_stride = 1;
+    smp.scale = (float)(C.P.dt * C.P.dt);
+    a.do_sample = o.q_adj ? 1 : 0;
+    a.smp = smp;
+    const bool accum = o.Z || o.hist;
+    int s_hi = nt - 1;
+    for (int k = nt - 1; k >= 1; --k) {
+        a.k = k;
+        a.cur = slot_ptr(C.ring, L, ns, k);
+        a.prev = slot_ptr(C.ring, L, ns, k + 1);
+        a.next = slot_ptr(C.ring, L, ns, k - 1);
+        TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
+        // lambda^{k-1} is known: w^k can be formed
+        if (accum && (s_hi - k + 1 == C.plan.block || k == 1)) {
+            if (o.hist)
+                TPX_HIP(prof(TPX_KERNEL_ACCUM_FULL, C.stream,
+                             [&] { return launch_accum_full(L, o.hist, C.ring, ns, k, s_hi, o.gpart, C.stream); }));
+            else
+                TPX_HIP(prof(TPX_KERNEL_ACCUM_ADJ, C.stream, [&] {
+                    return launch_accum_adj(L, C.ring, ns, k, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c, o.vbar,
+                                            o.gpart, C.stream);
+                }));
+            s_hi = k - 1;
+        }
+    }
+    if (o.q_adj) TPX_HIP(launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, smp, C.stream));
+    return TPX_OK;
+}
+
+const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, tpx_status *st) {
+    *st = TPX_OK;
+    if (pr->kind == TPX_PROBE_EXPLICIT) return pr->Z;
+    float *Z = (float *)(C.ws + C.plan.Z);
+    hipError_t e = launch_probe_gen(pr->kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream);
+    if (e != hipSuccess) *st = fail(TPX_E_DEVICE, std::string("probe generation: ") + hipGetErrorString(e));
+    return Z;
+}
+
+float probe_scale(const tpx_probe *pr) {
+    if (pr->kind == TPX_PROBE_IDENTITY) return 1.0f;
+    if (pr->kind == TPX_PROBE_EXPLICIT) return (float)pr->scale;
+    return (float)(1.0 / pr->r);
+}
+
+Mode mode_of(int32_t call, bool *ok) {
+    *ok = true;
+    switch (call) {
+    case TPX_CALL_FORWARD: return M_FORWARD;
+    case TPX_CALL_ADJOINT: return M_ADJOINT;
+    case TPX_CALL_GRADIENT_PROBED: return M_GRAD_PROBED;
+    case TPX_CALL_GRADIENT_FULL: return M_GRAD_FULL;
+    case TPX_CALL_FORWARD_PROBED: return M_FWD_PROBED;
+    case TPX_CALL_BACKWARD_PROBED: return M_BWD_PROBED;
+    default: *ok = false; return M_FORWARD;
+    }
+}
+
+template <class F>
+tpx_status guarded(F &&f) {
+    try {
+        return f();
+    } catch (const std::exception &e) {
+        return fail(TPX_E_INVAL, std::string("internal error: ") + e.what());
+    } catch (...) {
+        return fail(TPX_E_INVAL, "internal error");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tpx_last_error(void) { return g_err.c_str(); }
+const char *tpx_version(void) { return "tpx 0.1 gfx950"; }
+
+size_t tpx_workspace_bytes(int32_t call, const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe) {
+    size_t out = 0;
+    guarded([&]() -> tpx_status {
+        bool ok;
+        const Mode mode = mode_of(call, &ok);
+        if (!ok) return fail(TPX_E_INVAL, "unknown call id");
+        Problem P;
+        tpx_status st = make_problem(grid, geom, &P);
+        if (st != TPX_OK) return st;
+        const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
+        if (probed && (st = check_probe(P, probe)) != TPX_OK) return st;
+        out = make_plan(P, mode, probe).total;
+        return TPX_OK;
+    });
+    return out;
+}
+
+size_t tpx_state_bytes(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe) {
+    size_t out = 0;
+    guarded([&]() -> tpx_status {
+        Problem P;
+        tpx_status st = make_problem(grid, geom, &P);
+        if (st != TPX_OK) return st;
+        if ((st = check_probe(P, probe)) != TPX_OK) return st;
+        out = align_up((size_t)P.L.S * probe->r * P.L.nphys * 4);
+        return TPX_OK;
+    });
+    return out;
+}
+
+tpx_status tpx_forward(const tpx_grid *grid, const tpx_geom *geom, const float *m, float *d, void *ws,
+                       size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if (!d && geom && geom->nrec > 0) return fail(TPX_E_INVAL, "d must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, nullptr, M_FORWARD, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        return run_forward(C, geom->wavelet, d, nullptr, nullptr, 0, nullptr);
+    });
+}
+
+tpx_status tpx_adjoint(const tpx_grid *grid, const tpx_geom *geom, const float *m, const float *d_in, float *q_adj,
+                       void *ws, size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if ((!d_in && geom && geom->nrec > 0) || !q_adj) return fail(TPX_E_INVAL, "d_in and q_adj must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, nullptr, M_ADJOINT, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        AdjOut o;
+        o.q_adj = q_adj;
+        return run_adjoint(C, d_in, o);
+    });
+}
+
+tpx_status tpx_gradient_probed(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
+                               const float *d_obs, float *g, double *J, float *d_out, void *ws, size_t ws_bytes,
+                               void *stream) {
+    return guarded([&]() -> tpx_status {
+        if ((!d_obs && geom && geom->nrec > 0) || !g || !J) return fail(TPX_E_INVAL, "d_obs, g and J must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, probe, M_GRAD_PROBED, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        const Layout &L = C.P.L;
+        const float *Z = probe_matrix_dev(C, probe, &st);
+        if (st != TPX_OK) return st;
+        float *ubar = (float *)(C.ws + C.plan.ubar);
+        float *d = d_out ? d_out : (float *)(C.ws + C.plan.d);
+        float *res = (float *)(C.ws + C.plan.res);
+        st = run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, ubar);
+        if (st != TPX_OK) return st;
+        const int64_t ntr = (int64_t)L.S * C.P.nt * C.P.nrec;
+        const int parts = residual_parts(ntr);
+        TPX_HIP(launch_residual(d, d_obs, res, ntr, (double *)(C.ws + C.plan.parts), parts, J, C.stream));
+        AdjOut o;
+        o.Z = Z;
+        o.r = probe->r;
+        o.fold = probe->keep_vbar ? 0 : 1;
+        o.ubar = ubar;
+        o.c = probe_scale(probe);
+        o.vbar = probe->keep_vbar ? (float *)(C.ws + C.plan.vbar) : nullptr;
+        o.gpart = probe->keep_vbar ? nullptr : (float *)(C.ws + C.plan.gpart);
+        st = run_adjoint(C, res, o);
+        if (st != TPX_OK) return st;
+        if (probe->keep_vbar) TPX_HIP(launch_image_probed(L, probe->r, o.c, ubar, o.vbar, g, C.stream));
+        else TPX_HIP(launch_image_sum(L, o.gpart, g, C.stream));
+        return TPX_OK;
+    });
+}
+
+tpx_status tpx_gradient_full(const tpx_grid *grid, const tpx_geom *geom, const float *m, const float *d_obs, float *g,
+                             double *J, float *d_out, void *ws, size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if ((!d_obs && geom && geom->nrec > 0) || !g || !J) return fail(TPX_E_INVAL, "d_obs, g and J must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, nullptr, M_GRAD_FULL, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        const Layout &L = C.P.L;
+        float *hist = (float *)(C.ws + C.plan.hist);
+        float *d = d_out ? d_out : (float *)(C.ws + C.plan.d);
+        float *res = (float *)(C.ws + C.plan.res);
+        st = run_forward(C, geom->wavelet, d, hist, nullptr, 0, nullptr);
+        if (st != TPX_OK) return st;
+        const int64_t ntr = (int64_t)L.S * C.P.nt * C.P.nrec;
+        TPX_HIP(launch_residual(d, d_obs, res, ntr, (double *)(C.ws + C.plan.parts), residual_parts(ntr), J,
+                                C.stream));
+        AdjOut o;
+        o.hist = hist;
+        o.gpart = (float *)(C.ws + C.plan.gpart);
+        st = run_adjoint(C, res, o);
+        if (st != TPX_OK) return st;
+        TPX_HIP(launch_image_sum(L, o.gpart, g, C.stream));
+        return TPX_OK;
+    });
+}
+
+tpx_status tpx_forward_probed(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
+                              float *d, void *state, size_t state_bytes, void *ws, size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if ((!d && geom && geom->nrec > 0) || !state) return fail(TPX_E_INVAL, "d and state must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, probe, M_FWD_PROBED, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        const size_t need = align_up((size_t)C.P.L.S * probe->r * C.P.L.nphys * 4);
+        if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
+        const float *Z = probe_matrix_dev(C, probe, &st);
+        if (st != TPX_OK) return st;
+        return run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, (float *)state);
+    });
+}
+
+tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
+                               const float *grad_d, const void *state, size_t state_bytes, float *g, void *ws,
+                               size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if ((!grad_d && geom && geom->nrec > 0) || !state || !g) return fail(TPX_E_INVAL, "grad_d, state and g must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, probe, M_BWD_PROBED, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        const Layout &L = C.P.L;
+        const size_t need = align_up((size_t)L.S * probe->r * L.nphys * 4);
+        if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
+        const float *Z = probe_matrix_dev(C, probe, &st);
+        if (st != TPX_OK) return st;
+        AdjOut o;
+        o.Z = Z;
+        o.r = probe->r;
+        o.fold = probe->keep_vbar ? 0 : 1;
+        o.ubar = (const float *)state;
+        o.c = probe_scale(probe);
+        o.vbar = probe->keep_vbar ? (float *)(C.ws + C.plan.vbar) : nullptr;
+        o.gpart = probe->keep_vbar ? nullptr : (float *)(C.ws + C.plan.gpart);
+        st = run_adjoint(C, grad_d, o);
+        if (st != TPX_OK) return st;
+        if (probe->keep_vbar) TPX_HIP(launch_image_probed(L, probe->r, o.c, o.ubar, o.vbar, g, C.stream));
+        else TPX_HIP(launch_image_sum(L, o.gpart, g, C.stream));
+        return TPX_OK;
+    });
+}
+
+void tpx_profile_enable(int32_t on) {
+    Profiler &p = profiler();
+    std::lock_guard<std::mutex> lk(p.mu);
+    if (on) {
+        p.recs.clear();
+        p.used = 0;
+    }
+    p.on = on != 0;
+}
+
+tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches) {
+    return guarded([&]() -> tpx_status {
+        if (!total_ms || !launches) return fail(TPX_E_INVAL, "total_ms and launches must not be NULL");
+        Profiler &p = profiler();
+        std::lock_guard<std::mutex> lk(p.mu);
+        double tot = 0.0;
+        int64_t n = 0;
+        for (const ProfRec &r : p.recs) {
+            if (r.kind != kind) continue;
+            TPX_HIP(hipEventSynchronize(r.b));
+            float ms = 0.0f;
+            TPX_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            tot += ms;
+            ++n;
+        }
+        *total_ms = tot;
+        *launches = n;
+        return TPX_OK;
+    });
+}
+
+tpx_status tpx_check_workspace(const void *ws, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if (!ws) return fail(TPX_E_INVAL, "ws must not be NULL");
+        int32_t flags = 0;
+        TPX_HIP(hipStreamSynchronize((hipStream_t)stream));
+        TPX_HIP(hipMemcpy(&flags, ws, sizeof flags, hipMemcpyDeviceToHost));
+        if (flags & 1) return fail(TPX_E_NUMERIC, "the model holds a non-finite or non-positive value");
+        if (flags & 2) return fail(TPX_E_CFL, "the model holds velocities above damp_vmax (dt may be unstable)");
+        return TPX_OK;
+    });
+}
+
+tpx_status tpx_probe_matrix(const tpx_probe *probe, int32_t nt, int32_t shot, float *Z, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if (!probe || !Z) return fail(TPX_E_INVAL, "probe and Z must not be NULL");
+        if (nt < 1 || shot < 0 || probe->r < 1) return fail(TPX_E_INVAL, "nt >= 1, shot >= 0, r >= 1 required");
+        if (probe->kind == TPX_PROBE_EXPLICIT || probe->kind < 0 || probe->kind > 3)
+            return fail(TPX_E_INVAL, "tpx_probe_matrix generates Rademacher, Gauss-B64 or identity probes");
+        if (probe->kind == TPX_PROBE_IDENTITY && probe->r != nt) return fail(TPX_E_INVAL, "identity needs r == nt");
+        TPX_HIP(launch_probe_gen(probe->kind, probe->r, probe->seed, nt, shot, 1, Z, (hipStream_t)stream));
+        return TPX_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,141 @@
+// Internal declarations shared by the host runtime (runtime.cpp) and the
+// kernels (kernels.hip).  Not part of the public C-ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace tpx {
+
+// ---------------------------------------------------------------------------
+// Field layout in HBM.
+//
+// One wavefield "slot" holds all S shots: [shot][zg][yg][xg] with
+//   xg in [0, G0): the padded box starts at XO (a 128-byte aligned offset that
+//                  also serves as the left ghost border), pitch G0 is a
+//                  multiple of 32 floats;
+//   yg in [0, G1): 3D only, R ghost planes on each side (2D: G1 = 1);
+//   zg in [0, G2): R ghost rows on each side.
+// Ghost cells are zero forever (Dirichlet condition outside the padded box)
+// so the stencil kernels need no bounds tests on neighbour reads.
+// ---------------------------------------------------------------------------
+constexpr int XO = 32;
+
+// 2D step kernel tile: 64 (x) by 16 (z) outputs, 256 threads.
+constexpr int T2X = 64;
+constexpr int T2Z = 16;
+// 3D step kernel tile: 64 (x) by 4 (y) columns, marching T3Z planes in z.
+constexpr int T3X = 64;
+constexpr int T3Y = 4;
+constexpr int T3Z = 32;
+
+struct Layout {
+    int ndim;      // 2 or 3
+    int R;         // stencil half-width = order / 2
+    int nb;        // absorbing nodes per face
+    int S;         // shots in a slot
+    int64_t n[3];  // physical nodes x, y, z (2D: n[1] = 1)
+    int64_t P[3];  // padded box (2D: P[1] = 1)
+    int64_t G[3];  // allocated extents incl. ghosts: G[0] = pitch
+    int64_t oy;    // ghost offset along y (R in 3D, 0 in 2D)
+    int64_t shot_floats;  // G0 * G1 * G2
+    int64_t slot_floats;  // S * shot_floats
+    int64_t nphys;        // n0 * n1 * n2
+    int64_t npad;         // P0 * P1 * P2
+    // tiles of the step kernel (used by the injection tables)
+    int tile[3];
+    int64_t ntiles[3];
+    int64_t tiles_per_shot;
+
+    // offset (floats, within one shot) of padded node (ix, iy, iz)
+    __host__ __device__ inline int64_t pad_off(int64_t ix, int64_t iy, int64_t iz) const {
+        return ((iz + R) * G[1] + (iy + oy)) * G[0] + XO + ix;
+    }
+};
+
+// Stencil/physics constants passed to the step kernels.
+struct Physics {
+    float c[5];        // Laplacian weights divided by h^2 (c[0] centre per axis)
+    float hd_max;      // dmax * dt / 2 (damping at the outermost node, per axis)
+    float inv_nb;      // 1 / nbl (0 when nbl == 0)
+};
+
+// Point-source injection into one step: per (shot, tile) a list of target
+// points ("segments"), each with an ordered run of (source index, weight).
+struct InjectTables {
+    const int32_t *tile_ptr;  // [S * tiles_per_shot + 1] -> segment ranges
+    const int32_t *seg_local; // [nseg] local index within the tile
+    const int32_t *seg_ent;   // [nseg + 1] entry ranges (global, ascending)
+    const int32_t *ent_idx;   // [nent] source index (receiver id or 0)
+    const float *ent_w;       // [nent] interpolation weight
+};
+
+// Amplitudes injected at step k: amp[shot * shot_stride + k * k_stride + idx] * scale
+struct Amplitude {
+    const float *ptr;
+    int64_t shot_stride;
+    int64_t k_stride;
+    float scale;
+};
+
+// Sampling: per shot, nsmp points with a base offset and 2^D weights.
+struct SampleTables {
+    int32_t nsmp;             // samples per shot (receivers or 1 source)
+    const int32_t *base;      // [S][nsmp] offset of the base node within a shot field
+    const float *w;           // [S][nsmp][2^D]
+    float *out;               // out[shot * out_shot_stride + k * out_k_stride + i] = scale * sum
+    int64_t out_shot_stride;
+    int64_t out_k_stride;
+    float scale;
+};
+
+struct StepArgs {
+    const float *cur;   // u^k (slot base, shot 0)
+    const float *prev;  // u^{k-1}
+    float *next;        // u^{k+1}
+    const float *beta;  // dt^2 / m_pad, one shot-sized field
+    int k;              // time index of `cur` (selects amplitudes and sample rows)
+    int inject;         // 0/1
+    int do_sample;      // 0/1
+    InjectTables inj;
+    Amplitude amp;
+    SampleTables smp;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All are asynchronous on `stream`.
+// ---------------------------------------------------------------------------
+hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hipStream_t stream);
+hipError_t launch_sample_only(const Layout &L, const float *field, int k, const SampleTables &smp,
+                              hipStream_t stream);
+hipError_t launch_model_prep(const Layout &L, const float *m, double dt, float m_min, float *beta, int32_t *flags,
+                             hipStream_t stream);
+hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t stream);
+hipError_t launch_probe_gen(int kind, int r, uint64_t seed, int nt, int shot0, int nshots, float *Z,
+                            hipStream_t stream);
+hipError_t launch_probe_copy(const float *Zsrc, int64_t n, float *Zdst, hipStream_t stream);
+
+// ubar[shot][j][p] += sum_{s=s_lo}^{s_hi} Z[shot][s][j] * u^s[p]  (physical p)
+hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi,
+                            const float *Z, int nt, int r, float *ubar, hipStream_t stream);
+// w^s = lam^{s-1} - 2 lam^s + lam^{s+1} from the ring; either
+//   vbar[shot][j][p] += sum_s Z[shot][s][j] w^s[p]          (fold == 0), or
+//   gpart[shot][p]   += -c sum_s w^s[p] sum_j Z[s][j] ubar_j[p]   (fold == 1)
+hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi,
+                            const float *Z, int nt, int r, int fold, const float *ubar, float c, float *vbar,
+                            float *gpart, hipStream_t stream);
+// gpart[shot][p] += - sum_s u^s[p] w^s[p], u^s from the full history (slot s)
+hipError_t launch_accum_full(const Layout &L, const float *hist, const float *ring, int nslots, int s_lo,
+                             int s_hi, float *gpart, hipStream_t stream);
+// g[p] = sum_shot gpart[shot][p]   or   g[p] = -c sum_shot sum_j ubar vbar
+hipError_t launch_image_sum(const Layout &L, const float *gpart, float *g, hipStream_t stream);
+hipError_t launch_image_probed(const Layout &L, int r, float c, const float *ubar, const float *vbar, float *g,
+                               hipStream_t stream);
+// res = d - d_obs; J = 1/2 sum res^2 (deterministic two-pass FP64 reduction)
+hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_t n, double *partials,
+                           int nparts, double *J, hipStream_t stream);
+int residual_parts(int64_t n);
+
+}  // namespace tpx

@@ -1,0 +1,89 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol the public
+header declares, and rejects bad arguments on the host before any launch."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests.helpers import ensure_built
+
+ensure_built()
+
+from paper_2104_00794_amd import tpx  # noqa: E402
+
+
+def _geom(src, rec):
+    return tpx.Geometry(np.array(src, float), np.array(rec, float))
+
+
+def test_library_exports_every_header_symbol():
+    L = tpx.lib()
+    names = tpx.exported_names_in_header()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert tpx.version().startswith("tpx")
+
+
+GRID = dict(shape=(30, 40), h=10.0, dt=1.5, nt=100, order=8, nbl=5, damp_vmax=3.0)
+
+
+def _call_forward(grid, geom, ws_bytes=1 << 40):
+    # fake device pointers: validation fails on the host before anything is launched
+    L = tpx.lib()
+    g, ge = grid.c(), geom.c()
+    ge.wavelet = 0x1000
+    return L.tpx_forward(ctypes.byref(g), ctypes.byref(ge), 0x1000, 0x2000, 0x3000, ws_bytes, None)
+
+
+def test_cfl_rejected():
+    grid = tpx.Grid(**dict(GRID, dt=2.0))  # limit for order 8, 2D: 0.5546 * h / vmax = 1.849 ms
+    st = _call_forward(grid, _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]]))
+    assert st == tpx.E_CFL
+    assert "stability" in tpx.lib().tpx_last_error().decode()
+
+
+def test_geometry_outside_grid_rejected():
+    grid = tpx.Grid(**GRID)
+    st = _call_forward(grid, _geom([[100.0, 0, 50.0]], [[[400.0, 0, 20.0]]]))  # x max is 390 m
+    assert st == tpx.E_GEOM
+    st = _call_forward(grid, _geom([[-1.0, 0, 50.0]], [[[10.0, 0, 20.0]]]))
+    assert st == tpx.E_GEOM
+
+
+def test_workspace_too_small_rejected():
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]])
+    need = tpx.workspace_bytes(tpx.CALL_FORWARD, grid, geom)
+    assert _call_forward(grid, geom, ws_bytes=need - 1) == tpx.E_NOMEM
+
+
+@pytest.mark.parametrize("bad", [dict(order=6), dict(nt=1), dict(h=0.0), dict(nbl=-1), dict(damp_R=0.0)])
+def test_invalid_grid_rejected(bad):
+    grid = tpx.Grid(**dict(GRID, **bad))
+    assert _call_forward(grid, _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]])) == tpx.E_INVAL
+
+
+def test_workspace_bytes_by_call():
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0], [200.0, 0, 50.0]], [[[10.0, 0, 20.0]] * 3] * 2)
+    p = tpx.Probe(r=8)
+    fwd = tpx.workspace_bytes(tpx.CALL_FORWARD, grid, geom)
+    prb = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, p)
+    full = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom)
+    assert 0 < fwd < prb and fwd < full
+    # identity probes need r == nt
+    with pytest.raises(tpx.TpxError):
+        tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(kind="identity", r=8))
+    # probe accumulators are S * r * N_phys floats
+    assert tpx.state_bytes(grid, geom, p) >= 2 * 8 * 30 * 40 * 4
+
+
+def test_full_history_of_3d_config_exceeds_one_gpu():
+    # 401 x 401 x 301 nodes, nt = 2001: the stored forward history alone is > 288 GB
+    grid = tpx.Grid((301, 401, 401), h=12.5, dt=1.25, nt=2001, order=8, nbl=20, damp_vmax=4.0)
+    geom = _geom([[2500.0, 2500.0, 50.0]], [[[0.0, 0.0, 50.0]]])
+    full = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom)
+    probed = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=32))
+    assert full > 288e9
+    assert probed < 40e9

@@ -1,0 +1,236 @@
+"""GPU parity: the HIP library against the FP64 oracle on identical seeded
+inputs.  Bars: probes bit-exact; traces, adjoint outputs and gradients within
+relative L2 <= 1e-4 (FP32 on the GPU vs FP64 in the oracle).
+
+Sizes span several step-kernel tiles (64 x 16 in 2D, 64 x 4 columns with
+32-plane z chunks in 3D) with ragged edges, both stencil orders, several
+shots, off-grid and on-grid sources/receivers, and the edge cases nt = 2,
+no receivers, receivers on the last grid line.
+"""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.helpers import Case, cuda, ensure_built, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+if gpu_available():
+    ensure_built()
+
+import oracle  # noqa: E402
+from paper_2104_00794_amd import tpx  # noqa: E402
+from paper_2104_00794_amd.inputs import small_2d, small_3d, workload  # noqa: E402
+
+
+def _print_case(name, **kw):
+    print("[case]", name, kw, flush=True)
+
+
+# --------------------------------------------------------------------------- #
+# probes
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("kind", ["rademacher", "gauss_b64"])
+def test_probe_matrix_bit_exact(kind):
+    for seed, shot, nt, r in ((0, 0, 37, 5), (12, 7, 2401, 64), (2 ** 63 + 11, 3, 129, 32)):
+        _print_case("probe", kind=kind, seed=seed, shot=shot, nt=nt, r=r)
+        Zg = to_np(tpx.probe_matrix(tpx.Probe(kind=kind, r=r, seed=seed), nt, shot))
+        Zo = oracle.probe_matrix(kind, r, seed, nt, shot)
+        assert np.array_equal(Zg, Zo)
+
+
+def test_identity_probe_matrix():
+    Zg = to_np(tpx.probe_matrix(tpx.Probe(kind="identity", r=33), 33, 0))
+    assert np.array_equal(Zg, np.eye(33))
+
+
+# --------------------------------------------------------------------------- #
+# forward and adjoint
+# --------------------------------------------------------------------------- #
+
+CASES_2D = [
+    dict(nz=40, nx=150, order=8, nt=200, nbl=6, nshots=3, nrec=17),   # several x tiles, ragged
+    dict(nz=37, nx=29, order=4, nt=160, nbl=9, nshots=2, nrec=5),     # ragged in x and z
+]
+
+
+@pytest.mark.parametrize("kw", CASES_2D)
+def test_forward_traces_2d(kw):
+    _print_case("forward2d", **kw)
+    c = Case(small_2d(**kw))
+    d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
+    d_g = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    assert rel_l2(d_g, d_o) <= TOL
+
+
+def test_forward_traces_3d():
+    kw = dict(nz=40, ny=11, nx=70, nt=90, nbl=5, nshots=2, nrec=9)   # 2 z-chunks, ragged y/x tiles
+    _print_case("forward3d", **kw)
+    c = Case(small_3d(**kw))
+    d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
+    d_g = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    assert rel_l2(d_g, d_o) <= TOL
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_adjoint_matches_oracle_and_dot_test(ndim):
+    _print_case("adjoint", ndim=ndim)
+    c = Case(small_2d(nz=33, nx=70, nt=150) if ndim == 2 else small_3d(nt=70, nshots=2))
+    rng = np.random.default_rng(4)
+    d_in = rng.normal(size=(c.wl.nshots, c.wl.nt, c.rec.shape[1])).astype(np.float32).astype(np.float64)
+    q_o = oracle.adjoint(c.ogrid(), c.m_true, c.src, c.rec, d_in)
+    q_g = to_np(tpx.adjoint(c.tgrid(), c.tgeom(), cuda(c.m_true), cuda(d_in)))
+    assert rel_l2(q_g, q_o) <= TOL
+    # dot test on the GPU path alone
+    q = rng.normal(size=(c.wl.nshots, c.wl.nt)).astype(np.float32)
+    geom = tpx.Geometry(c.src, c.rec, cuda(q))
+    Fq = to_np(tpx.forward(c.tgrid(), geom, cuda(c.m_true)))
+    lhs, rhs = np.sum(Fq * d_in), np.sum(q.astype(np.float64) * q_g)
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
+
+
+def test_edge_cases_forward():
+    # nt = 2; receivers exactly on the last grid line and corner; one shot
+    wl = small_2d(nz=20, nx=21, nt=2, nshots=1, nrec=3)
+    X, Zd = (wl.shape[1] - 1) * wl.h, (wl.shape[0] - 1) * wl.h
+    wl = wl.with_(rec=[(X, 0.0, Zd), (0.0, 0.0, 0.0), (X / 2, 0.0, Zd)])
+    c = Case(wl)
+    d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
+    d_g = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    assert np.all(d_o[:, 0] == 0) and np.all(d_g[:, 0] == 0)
+    np.testing.assert_allclose(d_g, d_o, rtol=0, atol=1e-6 * max(np.abs(d_o).max(), 1e-30))
+    # longer record with the same edge receivers
+    c = Case(wl.with_(nt=120))
+    d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
+    d_g = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    assert rel_l2(d_g, d_o) <= TOL
+
+
+def test_no_receivers_gradient_is_zero():
+    wl = small_2d(nt=80).with_(rec=[])
+    c = Case(wl)
+    zero = np.zeros((wl.nshots, wl.nt, 0))
+    g, J = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=4, seed=1), cuda(c.m0), cuda(zero))
+    assert float(J.item()) == 0.0
+    assert np.all(to_np(g) == 0.0)
+
+
+# --------------------------------------------------------------------------- #
+# gradients
+# --------------------------------------------------------------------------- #
+
+def _grad_case(ndim):
+    if ndim == 2:
+        return Case(small_2d(nz=40, nx=150, nt=220, nshots=3, nrec=17))
+    return Case(small_3d(nz=40, ny=11, nx=70, nt=90, nshots=2, nrec=9))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_full_gradient_matches_oracle(ndim):
+    _print_case("grad_full", ndim=ndim)
+    c = _grad_case(ndim)
+    dobs = c.dobs_oracle()
+    g_o, J_o = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    g_g, J_g, d_g = tpx.gradient_full(c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs), return_traces=True)
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("kind", ["rademacher", "gauss_b64"])
+@pytest.mark.parametrize("keep_vbar", [False, True])
+def test_probed_gradient_matches_oracle(ndim, kind, keep_vbar):
+    _print_case("grad_probed", ndim=ndim, kind=kind, keep_vbar=keep_vbar)
+    c = _grad_case(ndim)
+    dobs = c.dobs_oracle()
+    r, seed = 6, 77
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, kind=kind, r=r, seed=seed)
+    probe = tpx.Probe(kind=kind, r=r, seed=seed, block=13, keep_vbar=keep_vbar)  # ragged time blocks
+    g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
+@pytest.mark.parametrize("r", [16, 64, 70])
+def test_probed_gradient_probe_counts(r):
+    # register-chunk boundaries of the contraction kernels (8/16/32/64 and beyond)
+    _print_case("grad_probed_r", r=r)
+    c = Case(small_2d(nz=30, nx=90, nt=150, nshots=2, nrec=11))
+    dobs = c.dobs_oracle()
+    g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=r, seed=5)
+    g_g, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=r, seed=5), cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+
+
+def test_identity_and_orthonormal_probes_give_exact_gradient():
+    c = Case(small_2d(nz=30, nx=70, nt=120, nshots=2, nrec=9))
+    dobs = c.dobs_oracle()
+    g_o, _ = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    g_id, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(kind="identity", r=c.wl.nt), cuda(c.m0),
+                                  cuda(dobs))
+    assert rel_l2(to_np(g_id), g_o) <= TOL
+    from scipy.fft import dct
+    Q = dct(np.eye(c.wl.nt), norm="ortho", axis=0)
+    Zs = np.stack([Q] * c.wl.nshots)
+    g_q, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(),
+                                 tpx.Probe(kind="explicit", r=c.wl.nt, Z=cuda(Zs), scale=1.0), cuda(c.m0),
+                                 cuda(dobs))
+    assert rel_l2(to_np(g_q), g_o) <= 2 * TOL
+
+
+def test_split_forward_backward_equals_gradient_call():
+    c = Case(small_2d(nz=30, nx=80, nt=140, nshots=2, nrec=9))
+    dobs = c.dobs_oracle()
+    probe = tpx.Probe(r=8, seed=3)
+    g1, J1, d1 = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs), return_traces=True)
+    d, state = tpx.forward_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0))
+    assert np.array_equal(to_np(d), to_np(d1))
+    g2 = tpx.backward_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), d - cuda(dobs), state)
+    assert np.array_equal(to_np(g1), to_np(g2))
+
+
+def test_deterministic_bitwise():
+    c = _grad_case(2)
+    dobs = c.dobs_oracle()
+    probe = tpx.Probe(r=8, seed=9)
+    a, Ja = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    b, Jb = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    assert np.array_equal(to_np(a), to_np(b)) and float(Ja.item()) == float(Jb.item())
+
+
+def test_workspace_flags_bad_model():
+    c = Case(small_2d(nz=20, nx=20, nt=20, nshots=1, nrec=3))
+    m = c.m_true.copy()
+    m[3, 4] = -1.0
+    ws = tpx.alloc_workspace(tpx.CALL_FORWARD, c.tgrid(), c.tgeom())
+    tpx.forward(c.tgrid(), c.tgeom(), cuda(m), ws=ws)
+    with pytest.raises(tpx.TpxError) as e:
+        tpx.check_workspace(ws)
+    assert e.value.status == tpx.E_NUMERIC
+    m = c.m_true.copy()
+    m[3, 4] = 0.5 / c.wl.vmax ** 2   # velocity above damp_vmax
+    tpx.forward(c.tgrid(), c.tgeom(), cuda(m), ws=ws)
+    with pytest.raises(tpx.TpxError) as e:
+        tpx.check_workspace(ws)
+    assert e.value.status == tpx.E_CFL
+
+
+# --------------------------------------------------------------------------- #
+# measured configurations
+# --------------------------------------------------------------------------- #
+
+def test_c0_two_layer_full_and_probed():
+    # 101 x 101, order 4, 1 shot, nt = 501, r = 8 Rademacher (seed 1)
+    _print_case("c0")
+    c = Case(workload("c0_two_layer_2d"))
+    dobs = c.dobs_oracle()
+    g_o, J_o = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    g_g, J_g = tpx.gradient_full(c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    gp_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=8, seed=c.wl.probe_seed)
+    gp_g, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=8, seed=c.wl.probe_seed), cuda(c.m0),
+                                  cuda(dobs))
+    assert rel_l2(to_np(gp_g), gp_o) <= TOL
