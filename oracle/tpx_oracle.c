@@ -146,30 +146,32 @@ static int stencil_weights(int order, double c[5]) {
     return 4;
 }
 
-/* out = L u over the padded box; values outside the box are zero (Dirichlet). */
+/* out = L u over the padded box; values outside the box are zero (Dirichlet).
+ * Per node: for each active axis, sum_{k=-R..R} c_|k| u[I + k e_axis] / h^2. */
 void orc_laplacian(const orc_grid *g, const double *u, double *out) {
     double c[5];
     const int R = stencil_weights(g->order, c);
     const int64_t P[3] = {padded(g, 0), padded(g, 1), padded(g, 2)};
+    const int64_t stride[3] = {1, P[0], P[0] * P[1]};
     const double ih2 = 1.0 / (g->h * g->h);
 #pragma omp parallel for schedule(static)
     for (int64_t iz = 0; iz < P[2]; ++iz)
         for (int64_t iy = 0; iy < P[1]; ++iy)
             for (int64_t ix = 0; ix < P[0]; ++ix) {
                 const int64_t I[3] = {ix, iy, iz};
+                const int64_t idx = pidx(g, ix, iy, iz);
                 double acc = 0.0;
                 for (int a = 0; a < 3; ++a) {
                     if (g->ndim == 2 && a == 1) continue;
                     double s = 0.0;
                     for (int k = -R; k <= R; ++k) {
-                        int64_t J[3] = {ix, iy, iz};
-                        J[a] = I[a] + k;
-                        if (J[a] < 0 || J[a] >= P[a]) continue;
-                        s += c[k < 0 ? -k : k] * u[pidx(g, J[0], J[1], J[2])];
+                        const int64_t J = I[a] + k;
+                        if (J < 0 || J >= P[a]) continue;
+                        s += c[k < 0 ? -k : k] * u[idx + k * stride[a]];
                     }
                     acc += s * ih2;
                 }
-                out[pidx(g, ix, iy, iz)] = acc;
+                out[idx] = acc;
             }
 }
 

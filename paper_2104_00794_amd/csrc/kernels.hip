@@ -26,7 +26,7 @@ __device__ __forceinline__ float layer_frac2(int64_t I, int64_t nphys, int nb, f
 //   (1 + hd) next = 2 cur - (1 - hd) prev + beta (lap + src),  hd = d dt / 2
 __device__ __forceinline__ float leapfrog(float cur, float prev, float beta, float lap, float src, float hd) {
     const float num = 2.0f * cur - (1.0f - hd) * prev + beta * (lap + src);
-    return hd == 0.0f ? num : num / (1.0f + hd);
+    return hd == 0.0f ? num : num * __builtin_amdgcn_rcpf(1.0f + hd);
 }
 
 // Sampling of `field` at this shot's points (receivers in the forward pass,
@@ -65,40 +65,78 @@ __device__ __forceinline__ void gather_sources(const InjectTables &inj, const Am
 
 // ---------------------------------------------------------------------------
 // 2D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 16 (z) tile of
-// outputs; u^k is staged with its R-wide halo in LDS, every thread produces
-// four outputs of one column.  Grid (x tiles, z tiles, shots).
+// outputs; every thread produces four outputs of one column.  All global
+// loads (u^k tile with its R-wide halo, u^{k-1}, beta) are issued before the
+// LDS barrier.  Blocks are numbered XCD-aware: the hardware hands block b to
+// XCD b mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8 gives every
+// XCD a contiguous run of tiles whose halos then hit in that XCD's L2.
+// Offsets within one shot field are 32-bit (a shot field is < 2^31 floats).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_logical_block(int nlogical) {
+    const int per = (int)gridDim.x >> 3;
+    const int hw = (int)blockIdx.x;
+    const int lid = (hw & 7) * per + (hw >> 3);
+    return lid < nlogical ? lid : -1;
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph, const StepArgs a) {
     constexpr int W = T2X + 2 * R;
     constexpr int H = T2Z + 2 * R;
+    constexpr int NL = (H + 3) / 4;
+    constexpr int NQ = T2Z / 4;
     __shared__ float tile[H][W];
     __shared__ float srcs[T2Z * T2X];
 
+    const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2];
+    const int lid = xcd_logical_block(ntx * ntz * L.S);
+    if (lid < 0) return;
+    const int bx = lid % ntx, bz = (lid / ntx) % ntz, shot = lid / (ntx * ntz);
+
     const int tid = threadIdx.x;
     const int lx = tid & 63, ly = tid >> 6;
-    const int shot = blockIdx.z;
-    const int64_t x0 = (int64_t)blockIdx.x * T2X, z0 = (int64_t)blockIdx.y * T2Z;
-    const int64_t G0 = L.G[0];
-    const float *cur = a.cur + shot * L.shot_floats;
+    const int x0 = bx * T2X, z0 = bz * T2Z;
+    const int G0 = (int)L.G[0], P0 = (int)L.P[0], P2 = (int)L.P[2];
+    const float *cur = a.cur + shot * L.shot_floats + XO;
+    const float *prev = a.prev + shot * L.shot_floats + XO;
+    const float *beta = a.beta + XO;
+    float *next = a.next + shot * L.shot_floats + XO;
 
-    for (int row = ly; row < H; row += 4) {
-        const int64_t gz = z0 - R + row;
-        const float *rowp = cur + (gz + R) * G0 + XO;
-        const bool zin = gz < L.P[2] + R;
-        for (int col = lx; col < W; col += 64) {
-            const int64_t gx = x0 - R + col;
-            tile[row][col] = (zin && gx < L.P[0] + R) ? rowp[gx] : 0.0f;
-        }
+    float t[NL], t2[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int row = ly + 4 * i, gz = z0 - R + row;
+        const bool rok = row < H && gz < P2 + R;
+        const int gx = x0 - R + lx, gx2 = gx + 64;
+        t[i] = (rok && gx < P0 + R) ? cur[(gz + R) * G0 + gx] : 0.0f;
+        t2[i] = (rok && lx < 2 * R && gx2 < P0 + R) ? cur[(gz + R) * G0 + gx2] : 0.0f;
+    }
+    float p[NQ], b[NQ];
+    const int x = x0 + lx;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int z = z0 + ly + 4 * q;
+        const bool ok = z < P2 && x < P0;
+        const int off = (z + R) * G0 + x;
+        p[q] = ok ? prev[off] : 0.0f;
+        b[q] = ok ? beta[off] : 0.0f;
     }
 
-    const int64_t tile_id = ((int64_t)shot * L.ntiles[2] + blockIdx.y) * L.ntiles[0] + blockIdx.x;
     int sb = 0, se = 0;
     if (a.inject) {
+        const int64_t tile_id = ((int64_t)shot * ntz + bz) * ntx + bx;
         sb = a.inj.tile_ptr[tile_id];
         se = a.inj.tile_ptr[tile_id + 1];
     }
     const bool has_src = sb < se;
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        const int row = ly + 4 * i;
+        if (row < H) {
+            tile[row][lx] = t[i];
+            if (lx < 2 * R) tile[row][64 + lx] = t2[i];
+        }
+    }
     if (has_src)
         for (int i = tid; i < T2Z * T2X; i += 256) srcs[i] = 0.0f;
     __syncthreads();
@@ -107,114 +145,164 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
         __syncthreads();
     }
 
-    float *next = a.next + shot * L.shot_floats;
-    const float *prev = a.prev + shot * L.shot_floats;
+    const float hx = layer_frac2(x, L.n[0], L.nb, ph.inv_nb);
 #pragma unroll
-    for (int q = 0; q < T2Z / 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
         const int lz = ly + 4 * q;
-        const int64_t z = z0 + lz, x = x0 + lx;
-        if (z >= L.P[2] || x >= L.P[0]) continue;
+        const int z = z0 + lz;
+        if (z >= P2 || x >= P0) continue;
         const float c = tile[lz + R][lx + R];
         float lap = 2.0f * ph.c[0] * c;
 #pragma unroll
         for (int k = 1; k <= R; ++k)
             lap += ph.c[k] * ((tile[lz + R][lx + R - k] + tile[lz + R][lx + R + k]) +
                               (tile[lz + R - k][lx + R] + tile[lz + R + k][lx + R]));
-        const int64_t off = (z + R) * G0 + XO + x;
-        const float hd = ph.hd_max * (layer_frac2(x, L.n[0], L.nb, ph.inv_nb) + layer_frac2(z, L.n[2], L.nb, ph.inv_nb));
+        const float hd = ph.hd_max * (hx + layer_frac2(z, L.n[2], L.nb, ph.inv_nb));
         const float s = has_src ? srcs[lz * T2X + lx] : 0.0f;
-        next[off] = leapfrog(c, prev[off], a.beta[off], lap, s, hd);
+        next[(z + R) * G0 + x] = leapfrog(c, p[q], b[q], lap, s, hd);
     }
 
-    if (a.do_sample)
-        sample_points<4>(L, cur, a.k, a.smp, shot, (int64_t)blockIdx.y * gridDim.x + blockIdx.x,
-                         (int64_t)gridDim.x * gridDim.y);
+    if (a.do_sample) {
+        const int per_shot = ntx * ntz;
+        sample_points<4>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bz * ntx + bx, per_shot);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// 3D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 4 (y) column
-// that marches T3Z planes in z.  z neighbours come from a register queue of
-// 2R+1 values per thread; x/y neighbours from the current plane staged in LDS
-// with its halo.  Grid (x tiles, y tiles, z chunks * shots).
+// 3D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 8 (y) column of
+// outputs (two y rows per thread) that marches T3Z planes in z.  z neighbours
+// come from per-thread register queues of 2R+1 values; x/y neighbours from
+// the current plane staged in LDS (double-buffered, one barrier per plane).
+// The halo of the next plane is prefetched into registers while the current
+// plane is computed.  Logical blocks are numbered XCD-aware as in 2D.
 // ---------------------------------------------------------------------------
 template <int R>
-__global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a, int zchunks) {
+__global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
     constexpr int W = T3X + 2 * R;
-    constexpr int H = T3Y + 2 * R;
-    __shared__ float plane_t[H][W];
-    __shared__ float srcs[T3Y * T3X];
+    constexpr int H = T3Y + 2 * R;   // 16 rows for R = 4
+    __shared__ float plane_t[2][H][W];
+    __shared__ float srcs2[2][T3Y * T3X];   // double-buffered like the plane
+
+    const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
+    const int nzc = (int)((L.P[2] + T3Z - 1) / T3Z);
+    const int lid = xcd_logical_block(ntx * nty * nzc * L.S);
+    if (lid < 0) return;
+    const int bx = lid % ntx, by = (lid / ntx) % nty, zc = (lid / (ntx * nty)) % nzc, shot = lid / (ntx * nty * nzc);
 
     const int tid = threadIdx.x;
     const int lx = tid & 63, ly = tid >> 6;
-    const int shot = blockIdx.z / zchunks;
-    const int zc = blockIdx.z % zchunks;
-    const int64_t x0 = (int64_t)blockIdx.x * T3X, y0 = (int64_t)blockIdx.y * T3Y;
-    const int64_t zc0 = (int64_t)zc * T3Z;
-    const int64_t x = x0 + lx, y = y0 + ly;
-    const int64_t G0 = L.G[0], PL = L.G[0] * L.G[1];
-    const float *cur = a.cur + shot * L.shot_floats;
-    const float *prev = a.prev + shot * L.shot_floats;
-    float *next = a.next + shot * L.shot_floats;
+    const int x0 = bx * T3X, y0 = by * T3Y, zc0 = zc * T3Z;
+    const int x = x0 + lx;
+    const int ya = y0 + ly, yb = y0 + ly + 4;            // the two y rows of this thread
+    const int G0 = (int)L.G[0], PL = (int)(L.G[0] * L.G[1]);
+    const int P0 = (int)L.P[0], P1 = (int)L.P[1], P2 = (int)L.P[2], oy = (int)L.oy;
+    const float *cur = a.cur + shot * L.shot_floats + XO;
+    const float *prev = a.prev + shot * L.shot_floats + XO;
+    const float *beta = a.beta + XO;
+    float *next = a.next + shot * L.shot_floats + XO;
 
-    const bool col_ok = x < L.P[0] + R && y < L.P[1] + R;  // readable column (ghosts included)
-    const bool out_ok = x < L.P[0] && y < L.P[1];
-    // pointer to (x, y, padded z = 0) of this column
-    const float *colp = cur + R * PL + (y + L.oy) * G0 + XO + x;
+    const bool xr = x < P0 + R;
+    const bool ca = xr && ya < P1 + R, cb = xr && yb < P1 + R;       // readable columns
+    const bool oa = x < P0 && ya < P1, ob = x < P0 && yb < P1;       // output columns
+    const int cola = (ya + oy) * G0 + x, colb = (yb + oy) * G0 + x;  // + (z + R) * PL
 
-    float q[2 * R + 1];
+    // halo of a plane: rows ly and ly + 12 (y0 - R + ly, y0 + 8 + ly), all 72 columns;
+    // rows 4 + ly and 8 + ly (the centre rows) only their x-halo columns.
+    const int hy0 = y0 - R + ly, hy1 = y0 + T3Y + ly;
+    const int hxa = x0 - R + lx;                     // columns 0..63 of the staged row
+    const int hxb = x0 - R + 64 + lx;                // columns 64..71 (lanes < 2R)
+    const int hxc = lx < R ? x0 - R + lx : x0 + T3X + (lx - R);  // x-halo of the centre rows (lanes < 2R)
+    const bool y0ok = hy0 < P1 + R, y1ok = hy1 < P1 + R;
+    auto load_halo = [&](int z, float h[6]) {
+        const int zo = (z + R) * PL;
+        h[0] = (y0ok && hxa < P0 + R) ? cur[zo + (hy0 + oy) * G0 + hxa] : 0.0f;
+        h[1] = (y0ok && lx < 2 * R && hxb < P0 + R) ? cur[zo + (hy0 + oy) * G0 + hxb] : 0.0f;
+        h[2] = (y1ok && hxa < P0 + R) ? cur[zo + (hy1 + oy) * G0 + hxa] : 0.0f;
+        h[3] = (y1ok && lx < 2 * R && hxb < P0 + R) ? cur[zo + (hy1 + oy) * G0 + hxb] : 0.0f;
+        h[4] = (lx < 2 * R && ya < P1 + R && hxc < P0 + R) ? cur[zo + (ya + oy) * G0 + hxc] : 0.0f;
+        h[5] = (lx < 2 * R && yb < P1 + R && hxc < P0 + R) ? cur[zo + (yb + oy) * G0 + hxc] : 0.0f;
+    };
+
+    float qa[2 * R + 1], qb[2 * R + 1];
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) {
-        const int64_t z = zc0 - R + i;
-        q[i] = (col_ok && z < L.P[2] + R) ? colp[z * PL] : 0.0f;
+        const int z = zc0 - R + i;
+        const bool zin = z < P2 + R;
+        qa[i] = (ca && zin) ? cur[(z + R) * PL + cola] : 0.0f;
+        qb[i] = (cb && zin) ? cur[(z + R) * PL + colb] : 0.0f;
     }
-    const float hdxy = layer_frac2(x, L.n[0], L.nb, ph.inv_nb) + layer_frac2(y, L.n[1], L.nb, ph.inv_nb);
+    float h[6];
+    load_halo(zc0, h);
+    const float hxy_a = layer_frac2(x, L.n[0], L.nb, ph.inv_nb) + layer_frac2(ya, L.n[1], L.nb, ph.inv_nb);
+    const float hxy_b = layer_frac2(x, L.n[0], L.nb, ph.inv_nb) + layer_frac2(yb, L.n[1], L.nb, ph.inv_nb);
 
     for (int lz = 0; lz < T3Z; ++lz) {
-        const int64_t z = zc0 + lz;
-        if (z >= L.P[2]) break;
-        q[2 * R] = (col_ok && z + R < L.P[2] + R) ? colp[(z + R) * PL] : 0.0f;
+        const int z = zc0 + lz;
+        if (z >= P2) break;
+        const int zo = (z + R) * PL;
+        qa[2 * R] = ca ? cur[zo + R * PL + cola] : 0.0f;   // z + R < P2 + R always
+        qb[2 * R] = cb ? cur[zo + R * PL + colb] : 0.0f;
+        const float pa = oa ? prev[zo + cola] : 0.0f, pb = ob ? prev[zo + colb] : 0.0f;
+        const float ba = oa ? beta[zo + cola] : 0.0f, bb = ob ? beta[zo + colb] : 0.0f;
 
-        __syncthreads();  // the previous plane is no longer read
-        const float *pz = cur + (z + R) * PL + XO;
-        for (int i = tid; i < H * W; i += 256) {
-            const int r = i / W, c = i - r * W;
-            const int64_t gy = y0 - R + r, gx = x0 - R + c;
-            plane_t[r][c] = (gy < L.P[1] + R && gx < L.P[0] + R) ? pz[(gy + L.oy) * G0 + gx] : 0.0f;
+        float(*pt)[W] = plane_t[lz & 1];
+        pt[ly][lx] = h[0];
+        if (lx < 2 * R) pt[ly][64 + lx] = h[1];
+        pt[T3Y + R + ly][lx] = h[2];
+        if (lx < 2 * R) pt[T3Y + R + ly][64 + lx] = h[3];
+        pt[R + ly][R + lx] = qa[R];
+        pt[R + 4 + ly][R + lx] = qb[R];
+        if (lx < 2 * R) {
+            const int hc = lx < R ? lx : T3X + lx;   // column in the staged row
+            pt[R + ly][hc] = h[4];
+            pt[R + 4 + ly][hc] = h[5];
         }
         int sb = 0, se = 0;
         if (a.inject) {
-            const int64_t tile_id = (((int64_t)shot * L.ntiles[2] + z) * L.ntiles[1] + blockIdx.y) * L.ntiles[0] +
-                                    blockIdx.x;
+            const int64_t tile_id = (((int64_t)shot * L.ntiles[2] + z) * nty + by) * ntx + bx;
             sb = a.inj.tile_ptr[tile_id];
             se = a.inj.tile_ptr[tile_id + 1];
         }
         const bool has_src = sb < se;
-        if (has_src) srcs[tid] = 0.0f;
+        float *srcs = srcs2[lz & 1];
+        if (has_src) {
+            srcs[tid] = 0.0f;
+            srcs[tid + 256] = 0.0f;
+        }
         __syncthreads();
         if (has_src) {
             gather_sources(a.inj, a.amp, shot, a.k, sb, se, srcs);
             __syncthreads();
         }
-        if (out_ok) {
-            const float c = q[R];
-            float lap = 3.0f * ph.c[0] * c;
+        if (z + 1 < P2 && lz + 1 < T3Z) load_halo(z + 1, h);   // prefetch, overlaps the compute below
+
+        float lapa = 3.0f * ph.c[0] * qa[R], lapb = 3.0f * ph.c[0] * qb[R];
 #pragma unroll
-            for (int k = 1; k <= R; ++k)
-                lap += ph.c[k] * ((plane_t[ly + R][lx + R - k] + plane_t[ly + R][lx + R + k]) +
-                                  (plane_t[ly + R - k][lx + R] + plane_t[ly + R + k][lx + R]) +
-                                  (q[R - k] + q[R + k]));
-            const int64_t off = (z + R) * PL + (y + L.oy) * G0 + XO + x;
-            const float hd = ph.hd_max * (hdxy + layer_frac2(z, L.n[2], L.nb, ph.inv_nb));
+        for (int k = 1; k <= R; ++k) {
+            lapa += ph.c[k] * ((pt[R + ly][R + lx - k] + pt[R + ly][R + lx + k]) +
+                               (pt[R + ly - k][R + lx] + pt[R + ly + k][R + lx]) + (qa[R - k] + qa[R + k]));
+            lapb += ph.c[k] * ((pt[R + 4 + ly][R + lx - k] + pt[R + 4 + ly][R + lx + k]) +
+                               (pt[R + 4 + ly - k][R + lx] + pt[R + 4 + ly + k][R + lx]) + (qb[R - k] + qb[R + k]));
+        }
+        const float hz = layer_frac2(z, L.n[2], L.nb, ph.inv_nb);
+        if (oa) {
             const float s = has_src ? srcs[ly * T3X + lx] : 0.0f;
-            next[off] = leapfrog(c, prev[off], a.beta[off], lap, s, hd);
+            next[zo + cola] = leapfrog(qa[R], pa, ba, lapa, s, ph.hd_max * (hxy_a + hz));
+        }
+        if (ob) {
+            const float s = has_src ? srcs[(ly + 4) * T3X + lx] : 0.0f;
+            next[zo + colb] = leapfrog(qb[R], pb, bb, lapb, s, ph.hd_max * (hxy_b + hz));
         }
 #pragma unroll
-        for (int i = 0; i < 2 * R; ++i) q[i] = q[i + 1];
+        for (int i = 0; i < 2 * R; ++i) {
+            qa[i] = qa[i + 1];
+            qb[i] = qb[i + 1];
+        }
     }
 
     if (a.do_sample) {
-        const int64_t bis = ((int64_t)zc * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        sample_points<8>(L, cur, a.k, a.smp, shot, bis, (int64_t)gridDim.x * gridDim.y * zchunks);
+        const int per_shot = ntx * nty * nzc;
+        sample_points<8>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, (zc * nty + by) * ntx + bx, per_shot);
     }
 }
 
@@ -226,14 +314,16 @@ __global__ __launch_bounds__(256) void k_sample(const Layout L, const float *fie
 
 hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hipStream_t stream) {
     if (L.ndim == 2) {
-        dim3 grid((unsigned)L.ntiles[0], (unsigned)L.ntiles[2], (unsigned)L.S);
+        const int64_t nlog = L.ntiles[0] * L.ntiles[2] * L.S;
+        dim3 grid((unsigned)((nlog + 7) / 8 * 8));
         if (L.R == 2) hipLaunchKernelGGL(k_step2d<2>, grid, dim3(256), 0, stream, L, ph, a);
         else hipLaunchKernelGGL(k_step2d<4>, grid, dim3(256), 0, stream, L, ph, a);
     } else {
-        const int zchunks = (int)((L.P[2] + T3Z - 1) / T3Z);
-        dim3 grid((unsigned)L.ntiles[0], (unsigned)L.ntiles[1], (unsigned)(zchunks * L.S));
-        if (L.R == 2) hipLaunchKernelGGL(k_step3d<2>, grid, dim3(256), 0, stream, L, ph, a, zchunks);
-        else hipLaunchKernelGGL(k_step3d<4>, grid, dim3(256), 0, stream, L, ph, a, zchunks);
+        const int64_t zchunks = (L.P[2] + T3Z - 1) / T3Z;
+        const int64_t nlog = L.ntiles[0] * L.ntiles[1] * zchunks * L.S;
+        dim3 grid((unsigned)((nlog + 7) / 8 * 8));
+        if (L.R == 2) hipLaunchKernelGGL(k_step3d<2>, grid, dim3(256), 0, stream, L, ph, a);
+        else hipLaunchKernelGGL(k_step3d<4>, grid, dim3(256), 0, stream, L, ph, a);
     }
     return hipGetLastError();
 }
@@ -333,7 +423,7 @@ __global__ __launch_bounds__(256) void k_probe_gen(int kind, int r, uint64_t see
     } else {
         const uint64_t w = philox_w0((uint64_t)t + 1, (uint64_t)j, (uint64_t)shot, 0, seed, 0);
         if (kind == 0) z = (w >> 63) ? -1.0f : 1.0f;
-        else z = (float)(__popcll(w) - 32) * 0.25f;
+        else z = (float)((int)__popcll(w) - 32) * 0.25f;
     }
     Z[(int64_t)blockIdx.y * per_shot + i] = z;
 }
@@ -366,20 +456,22 @@ hipError_t launch_probe_copy(const float *Zsrc, int64_t n, float *Zdst, hipStrea
 // Grid (x chunks of 256, ny * nz rows, shots).
 // ---------------------------------------------------------------------------
 struct PointIndex {
-    int64_t off;  // offset within a shot field
-    int64_t p;    // flat physical index
+    int off;     // offset within a shot field
+    int64_t p;   // flat physical index
     bool ok;
 };
 
+// Block = 64 (x) by 4 (rows of [z][y]); grid (x chunks, row chunks, shots).
 __device__ __forceinline__ PointIndex point_index(const Layout &L) {
     PointIndex pi;
-    const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t row = blockIdx.y;
-    const int64_t z = row / L.n[1], y = row - z * L.n[1];
-    pi.ok = x < L.n[0];
-    const int64_t oyb = L.ndim == 3 ? L.nb : 0;
-    pi.off = L.pad_off(x + L.nb, y + oyb, z + L.nb);
-    pi.p = row * L.n[0] + x;
+    const int x = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
+    const int row = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
+    const int n0 = (int)L.n[0], n1 = (int)L.n[1], rows = (int)(L.n[1] * L.n[2]);
+    pi.ok = x < n0 && row < rows;
+    const int z = row / n1, y = row - z * n1;
+    const int oyb = L.ndim == 3 ? L.nb : 0;
+    pi.off = (int)L.pad_off(x + L.nb, y + oyb, z + L.nb);
+    pi.p = (int64_t)row * n0 + x;
     return pi;
 }
 
@@ -396,12 +488,15 @@ __global__ __launch_bounds__(256) void k_accum_fwd(const Layout L, const float *
         float acc[RC];
 #pragma unroll
         for (int j = 0; j < RC; ++j) acc[j] = 0.0f;
+        int slot = s_lo % nslots;
+#pragma unroll 4
         for (int s = s_lo; s <= s_hi; ++s) {
-            const float v = base[(int64_t)(s % nslots) * L.slot_floats];
+            const float v = base[(int64_t)slot * L.slot_floats];
             const float *zr = Z + ((int64_t)shot * nt + s) * r + j0;
 #pragma unroll
             for (int j = 0; j < RC; ++j)
-                if (j < rc) acc[j] += zr[j] * v;
+                if (j < rc) acc[j] = fmaf(zr[j], v, acc[j]);
+            slot = slot + 1 == nslots ? 0 : slot + 1;
         }
         float *ub = ubar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
 #pragma unroll
@@ -435,23 +530,28 @@ __global__ __launch_bounds__(256) void k_accum_adj(const Layout L, const float *
             for (int j = 0; j < RC; ++j)
                 if (j < rc) u[j] = ub[(int64_t)j * L.nphys];
         }
-        float lm = base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats];
-        float l0 = base[(int64_t)(s_lo % nslots) * L.slot_floats];
+        int slot = (s_lo - 1) % nslots;
+        float lm = base[(int64_t)slot * L.slot_floats];
+        slot = slot + 1 == nslots ? 0 : slot + 1;
+        float l0 = base[(int64_t)slot * L.slot_floats];
+        slot = slot + 1 == nslots ? 0 : slot + 1;
         float fsum = 0.0f;
+#pragma unroll 4
         for (int s = s_lo; s <= s_hi; ++s) {
-            const float lp = base[(int64_t)((s + 1) % nslots) * L.slot_floats];
+            const float lp = base[(int64_t)slot * L.slot_floats];
+            slot = slot + 1 == nslots ? 0 : slot + 1;
             const float w = (lm - 2.0f * l0) + lp;
             const float *zr = Z + ((int64_t)shot * nt + s) * r + j0;
             if (FOLD) {
                 float t = 0.0f;
 #pragma unroll
                 for (int j = 0; j < RC; ++j)
-                    if (j < rc) t += zr[j] * u[j];
-                fsum += w * t;
+                    if (j < rc) t = fmaf(zr[j], u[j], t);
+                fsum = fmaf(w, t, fsum);
             } else {
 #pragma unroll
                 for (int j = 0; j < RC; ++j)
-                    if (j < rc) acc[j] += zr[j] * w;
+                    if (j < rc) acc[j] = fmaf(zr[j], w, acc[j]);
             }
             lm = l0;
             l0 = lp;
@@ -476,13 +576,18 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
     const int shot = blockIdx.z;
     const float *hb = hist + shot * L.shot_floats + pi.off;
     const float *base = ring + shot * L.shot_floats + pi.off;
-    float lm = base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats];
-    float l0 = base[(int64_t)(s_lo % nslots) * L.slot_floats];
+    int slot = (s_lo - 1) % nslots;
+    float lm = base[(int64_t)slot * L.slot_floats];
+    slot = slot + 1 == nslots ? 0 : slot + 1;
+    float l0 = base[(int64_t)slot * L.slot_floats];
+    slot = slot + 1 == nslots ? 0 : slot + 1;
     float acc = 0.0f;
+#pragma unroll 4
     for (int s = s_lo; s <= s_hi; ++s) {
-        const float lp = base[(int64_t)((s + 1) % nslots) * L.slot_floats];
+        const float lp = base[(int64_t)slot * L.slot_floats];
+        slot = slot + 1 == nslots ? 0 : slot + 1;
         const float w = (lm - 2.0f * l0) + lp;
-        acc += hb[(int64_t)s * L.slot_floats] * w;
+        acc = fmaf(hb[(int64_t)s * L.slot_floats], w, acc);
         lm = l0;
         l0 = lp;
     }
@@ -490,7 +595,7 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
 }
 
 static dim3 point_grid(const Layout &L) {
-    return dim3((unsigned)((L.n[0] + 255) / 256), (unsigned)(L.n[1] * L.n[2]), (unsigned)L.S);
+    return dim3((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] * L.n[2] + 3) / 4), (unsigned)L.S);
 }
 
 hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,

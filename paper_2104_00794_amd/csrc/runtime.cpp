@@ -366,8 +366,13 @@ tpx_status build_tables(const Problem &P, const tpx_grid *g, const tpx_geom *geo
 // workspace plan
 // ---------------------------------------------------------------------------
 
-int default_block(int r, int nt) {
-    int b = r <= 16 ? 32 : 64;
+// Time steps buffered per probe contraction: the accumulators' read-modify-
+// write costs 8 r / b bytes per point-step, the ring costs (b + 2) slots.
+int default_block(const Layout &L, int nt) {
+    const double slot_bytes = (double)L.slot_floats * 4.0;
+    const double cap = 24e9;
+    int b = 128;
+    while (b > 16 && (b + 2) * slot_bytes > cap) b /= 2;
     if (b > nt - 1) b = nt - 1;
     if (b < 1) b = 1;
     return b;
@@ -396,7 +401,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr) {
     memset(&p, 0, sizeof p);
     const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
     const int r = probed ? pr->r : 0;
-    p.block = default_block(r, P.nt);
+    p.block = default_block(L, P.nt);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
     p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? 3 : p.block + 2;

@@ -26,9 +26,9 @@ constexpr int XO = 32;
 // 2D step kernel tile: 64 (x) by 16 (z) outputs, 256 threads.
 constexpr int T2X = 64;
 constexpr int T2Z = 16;
-// 3D step kernel tile: 64 (x) by 4 (y) columns, marching T3Z planes in z.
+// 3D step kernel tile: 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
-constexpr int T3Y = 4;
+constexpr int T3Y = 8;
 constexpr int T3Z = 32;
 
 struct Layout {

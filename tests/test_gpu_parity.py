@@ -2,7 +2,7 @@
 inputs.  Bars: probes bit-exact; traces, adjoint outputs and gradients within
 relative L2 <= 1e-4 (FP32 on the GPU vs FP64 in the oracle).
 
-Sizes span several step-kernel tiles (64 x 16 in 2D, 64 x 4 columns with
+Sizes span several step-kernel tiles (64 x 16 in 2D, 64 x 8 columns with
 32-plane z chunks in 3D) with ragged edges, both stencil orders, several
 shots, off-grid and on-grid sources/receivers, and the edge cases nt = 2,
 no receivers, receivers on the last grid line.
@@ -234,3 +234,79 @@ def test_c0_two_layer_full_and_probed():
     gp_g, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=8, seed=c.wl.probe_seed), cuda(c.m0),
                                   cuda(dobs))
     assert rel_l2(to_np(gp_g), gp_o) <= TOL
+
+
+def test_3d_sources_across_z_chunk_boundary_and_dense_receivers():
+    # receivers straddle the boundary between the first two 32-plane z chunks
+    # (padded z = 31.5) and sit 0.37 h apart, so several share injection nodes
+    wl = small_3d(nz=48, ny=12, nx=40, nt=80, nbl=5, nshots=2, nrec=4)
+    zc = (32 - wl.nbl - 0.5) * wl.h
+    rec = [(3.0 + 0.37 * wl.h * i, 0.5 * (wl.shape[1] - 1) * wl.h, zc) for i in range(30)]
+    wl = wl.with_(rec=rec)
+    _print_case("3d_chunk_boundary")
+    c = Case(wl)
+    dobs = c.dobs_oracle()
+    d_g = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    assert rel_l2(d_g, dobs) <= TOL
+    g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=8, seed=2)
+    g_g, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=8, seed=2, block=7), cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+
+
+def test_2d_dense_off_grid_receivers():
+    wl = small_2d(nz=30, nx=90, nt=150, nshots=2, nrec=4)
+    rec = [(5.0 + 0.37 * wl.h * i, 0.0, 3.3 * wl.h) for i in range(150)]
+    wl = wl.with_(rec=rec)
+    c = Case(wl)
+    dobs = c.dobs_oracle()
+    g_o, _ = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    g_g, _ = tpx.gradient_full(c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+
+
+def test_c1_full_configuration():
+    # 801 x 301, 16 shots batched in one launch, order 8, nt = 2401, r = 16
+    # Rademacher (the benchmarked launch configuration), against the oracle
+    _print_case("c1_full")
+    wl = workload("c1_layered_2d_16shots")
+    c = Case(wl)
+    d_true_g = tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true))
+    # sampled traces: shots 0 and 15 computed by the oracle one by one
+    for s in (0, 15):
+        d_o = oracle.forward(c.ogrid(), c.m_true, c.src[s:s + 1], c.rec[s:s + 1], c.wav[s:s + 1])
+        assert rel_l2(to_np(d_true_g[s:s + 1]), d_o) <= TOL
+    dobs = to_np(d_true_g)
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=wl.r, seed=wl.probe_seed)
+    g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=wl.r, seed=wl.probe_seed), cuda(c.m0),
+                                   cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
+def test_c3_full_grid_truncated_record():
+    # 401 x 401 x 301 at 12.5 m (the 3D configuration's grid and launch shape),
+    # 40,401 receivers, r = 32; record truncated to 40 steps (30 Hz wavelet)
+    # so the FP64 oracle finishes in about a minute; the gradient is compared
+    # at 4096 sampled points computed by the oracle one by one.
+    _print_case("c3_truncated")
+    wl = workload("c3_layered_3d").with_(nt=40, f_khz=0.03)
+    c = Case(wl)
+    d_g = tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true))
+    d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
+    assert rel_l2(to_np(d_g), d_o) <= TOL
+    dobs = np.zeros_like(d_o)
+    rng = np.random.default_rng(0)
+    # sample points near the source where the wavefield is non-zero after 70 steps
+    nz, ny, nx = wl.shape
+    zz = rng.integers(0, 12, 4096)
+    yy = rng.integers(190, 211, 4096)
+    xx = rng.integers(190, 211, 4096)
+    pts = (zz * ny + yy) * nx + xx
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=wl.r, seed=wl.probe_seed,
+                                      points=pts)
+    g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=wl.r, seed=wl.probe_seed), cuda(c.m0),
+                                   cuda(dobs))
+    g_s = to_np(g_g).reshape(-1)[pts]
+    assert np.linalg.norm(g_o) > 0
+    assert rel_l2(g_s, g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
