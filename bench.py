@@ -142,7 +142,9 @@ def main():
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, r, kind, args.cpu_nt or wl.nt)
+        # about 10-30 s of oracle work: the full record of one 2D shot, or a
+        # short window of the 3D record
+        cpu = cpu_baseline(wl, r, kind, args.cpu_nt or (wl.nt if wl.ndim == 2 else 24))
 
     out = {
         "metric": "GPts/s fwd+adj with r-probe accumulation (%HBM roofline); gradient p50/p99 latency",

@@ -14,8 +14,8 @@ namespace tpx {
 // ---------------------------------------------------------------------------
 
 // (distance into the absorbing layer / nbl)^2 along one axis, padded index I
-__device__ __forceinline__ float layer_frac2(int64_t I, int64_t nphys, int nb, float inv_nb) {
-    int64_t into = 0;
+__device__ __forceinline__ float layer_frac2(int I, int nphys, int nb, float inv_nb) {
+    int into = 0;
     if (I < nb) into = nb - I;
     else if (I > nb + nphys - 1) into = I - (nb + nphys - 1);
     const float d = (float)into * inv_nb;
@@ -26,7 +26,7 @@ __device__ __forceinline__ float layer_frac2(int64_t I, int64_t nphys, int nb, f
 //   (1 + hd) next = 2 cur - (1 - hd) prev + beta (lap + src),  hd = d dt / 2
 __device__ __forceinline__ float leapfrog(float cur, float prev, float beta, float lap, float src, float hd) {
     const float num = 2.0f * cur - (1.0f - hd) * prev + beta * (lap + src);
-    return hd == 0.0f ? num : num * __builtin_amdgcn_rcpf(1.0f + hd);
+    return num * __builtin_amdgcn_rcpf(1.0f + hd);   // rcp(1) = 1 exactly in the interior
 }
 
 // Sampling of `field` at this shot's points (receivers in the forward pass,
@@ -50,24 +50,23 @@ __device__ __forceinline__ void sample_points(const Layout &L, const float *fiel
     }
 }
 
-// Gather of the point-source term of one injection tile into LDS: one thread
-// per target point, entries summed in their stored order.
-__device__ __forceinline__ void gather_sources(const InjectTables &inj, const Amplitude &amp, int shot, int k,
-                                               int sb, int se, float *srcs) {
-    const float *a = amp.ptr + shot * amp.shot_stride + (int64_t)k * amp.k_stride;
-    for (int s = sb + (int)threadIdx.x; s < se; s += blockDim.x) {
-        float acc = 0.0f;
-        const int e1 = inj.seg_ent[s + 1];
-        for (int e = inj.seg_ent[s]; e < e1; ++e) acc += inj.ent_w[e] * a[inj.ent_idx[e]];
-        srcs[inj.seg_local[s]] = acc * amp.scale;
-    }
+// Source term of one injection segment (one target node): its entries
+// summed in their stored order.  Every argument is uniform across the block,
+// so the whole block evaluates it redundantly with scalar loads and the single
+// thread that owns the node adds it to its output.
+__device__ __forceinline__ float segment_value(const InjectTables &inj, const float *a, float scale, int sg) {
+    float acc = 0.0f;
+    const int e1 = inj.seg_ent[sg + 1];
+    for (int e = inj.seg_ent[sg]; e < e1; ++e) acc += inj.ent_w[e] * a[inj.ent_idx[e]];
+    return acc * scale;
 }
 
 // ---------------------------------------------------------------------------
-// 2D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 16 (z) tile of
-// outputs; every thread produces four outputs of one column.  All global
+// 2D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 32 (z) tile of
+// outputs; every thread produces eight outputs of one column.  All global
 // loads (u^k tile with its R-wide halo, u^{k-1}, beta) are issued before the
-// LDS barrier.  Blocks are numbered XCD-aware: the hardware hands block b to
+// LDS barrier.  Only nodes of the padded box are read (outside it the field
+// is zero by definition), so ghost cells of the buffers need no clearing.  Blocks are numbered XCD-aware: the hardware hands block b to
 // XCD b mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8 gives every
 // XCD a contiguous run of tiles whose halos then hit in that XCD's L2.
 // Offsets within one shot field are 32-bit (a shot field is < 2^31 floats).
@@ -86,7 +85,6 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
     constexpr int NL = (H + 3) / 4;
     constexpr int NQ = T2Z / 4;
     __shared__ float tile[H][W];
-    __shared__ float srcs[T2Z * T2X];
 
     const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2];
     const int lid = xcd_logical_block(ntx * ntz * L.S);
@@ -106,10 +104,10 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         const int row = ly + 4 * i, gz = z0 - R + row;
-        const bool rok = row < H && gz < P2 + R;
+        const bool rok = row < H && gz >= 0 && gz < P2;
         const int gx = x0 - R + lx, gx2 = gx + 64;
-        t[i] = (rok && gx < P0 + R) ? cur[(gz + R) * G0 + gx] : 0.0f;
-        t2[i] = (rok && lx < 2 * R && gx2 < P0 + R) ? cur[(gz + R) * G0 + gx2] : 0.0f;
+        t[i] = (rok && gx >= 0 && gx < P0) ? cur[(gz + R) * G0 + gx] : 0.0f;
+        t2[i] = (rok && lx < 2 * R && gx2 < P0) ? cur[(gz + R) * G0 + gx2] : 0.0f;
     }
     float p[NQ], b[NQ];
     const int x = x0 + lx;
@@ -121,14 +119,6 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
         p[q] = ok ? prev[off] : 0.0f;
         b[q] = ok ? beta[off] : 0.0f;
     }
-
-    int sb = 0, se = 0;
-    if (a.inject) {
-        const int64_t tile_id = ((int64_t)shot * ntz + bz) * ntx + bx;
-        sb = a.inj.tile_ptr[tile_id];
-        se = a.inj.tile_ptr[tile_id + 1];
-    }
-    const bool has_src = sb < se;
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         const int row = ly + 4 * i;
@@ -137,15 +127,31 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
             if (lx < 2 * R) tile[row][64 + lx] = t2[i];
         }
     }
-    if (has_src)
-        for (int i = tid; i < T2Z * T2X; i += 256) srcs[i] = 0.0f;
-    __syncthreads();
-    if (has_src) {
-        gather_sources(a.inj, a.amp, shot, a.k, sb, se, srcs);
-        __syncthreads();
-    }
 
-    const float hx = layer_frac2(x, L.n[0], L.nb, ph.inv_nb);
+    // point sources of this tile (rare): per target node one owning thread
+    float src[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) src[q] = 0.0f;
+    if (a.inject) {
+        const int64_t tile_id = ((int64_t)shot * ntz + bz) * ntx + bx;
+        const int sb = a.inj.tile_ptr[tile_id], se = a.inj.tile_ptr[tile_id + 1];
+        if (sb < se) {
+            const float *amp = a.amp.ptr + shot * a.amp.shot_stride + (int64_t)a.k * a.amp.k_stride;
+            for (int sg = sb; sg < se; ++sg) {
+                const int loc = a.inj.seg_local[sg];          // lz * 64 + lx of the target node
+                const float v = segment_value(a.inj, amp, a.amp.scale, sg);
+                const int lz = loc >> 6;
+                if ((loc & 63) == lx && (lz & 3) == ly) {
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if ((lz >> 2) == q) src[q] += v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    const float hx = layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int lz = ly + 4 * q;
@@ -157,9 +163,8 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
         for (int k = 1; k <= R; ++k)
             lap += ph.c[k] * ((tile[lz + R][lx + R - k] + tile[lz + R][lx + R + k]) +
                               (tile[lz + R - k][lx + R] + tile[lz + R + k][lx + R]));
-        const float hd = ph.hd_max * (hx + layer_frac2(z, L.n[2], L.nb, ph.inv_nb));
-        const float s = has_src ? srcs[lz * T2X + lx] : 0.0f;
-        next[(z + R) * G0 + x] = leapfrog(c, p[q], b[q], lap, s, hd);
+        const float hd = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
+        next[(z + R) * G0 + x] = leapfrog(c, p[q], b[q], lap, src[q], hd);
     }
 
     if (a.do_sample) {
@@ -174,14 +179,14 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
 // come from per-thread register queues of 2R+1 values; x/y neighbours from
 // the current plane staged in LDS (double-buffered, one barrier per plane).
 // The halo of the next plane is prefetched into registers while the current
-// plane is computed.  Logical blocks are numbered XCD-aware as in 2D.
+// plane is computed.  Logical blocks are numbered XCD-aware as in 2D; only
+// nodes of the padded box are read.
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
     constexpr int W = T3X + 2 * R;
     constexpr int H = T3Y + 2 * R;   // 16 rows for R = 4
     __shared__ float plane_t[2][H][W];
-    __shared__ float srcs2[2][T3Y * T3X];   // double-buffered like the plane
 
     const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
     const int nzc = (int)((L.P[2] + T3Z - 1) / T3Z);
@@ -201,9 +206,8 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
     const float *beta = a.beta + XO;
     float *next = a.next + shot * L.shot_floats + XO;
 
-    const bool xr = x < P0 + R;
-    const bool ca = xr && ya < P1 + R, cb = xr && yb < P1 + R;       // readable columns
-    const bool oa = x < P0 && ya < P1, ob = x < P0 && yb < P1;       // output columns
+    const bool oa = x < P0 && ya < P1, ob = x < P0 && yb < P1;       // columns inside the box
+    const bool ca = oa, cb = ob;
     const int cola = (ya + oy) * G0 + x, colb = (yb + oy) * G0 + x;  // + (z + R) * PL
 
     // halo of a plane: rows ly and ly + 12 (y0 - R + ly, y0 + 8 + ly), all 72 columns;
@@ -212,36 +216,40 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
     const int hxa = x0 - R + lx;                     // columns 0..63 of the staged row
     const int hxb = x0 - R + 64 + lx;                // columns 64..71 (lanes < 2R)
     const int hxc = lx < R ? x0 - R + lx : x0 + T3X + (lx - R);  // x-halo of the centre rows (lanes < 2R)
-    const bool y0ok = hy0 < P1 + R, y1ok = hy1 < P1 + R;
+    const bool y0ok = hy0 >= 0 && hy0 < P1, y1ok = hy1 < P1;
+    const bool xaok = hxa >= 0 && hxa < P0, xbok = lx < 2 * R && hxb < P0;
+    const bool xcok = lx < 2 * R && hxc >= 0 && hxc < P0;
     auto load_halo = [&](int z, float h[6]) {
         const int zo = (z + R) * PL;
-        h[0] = (y0ok && hxa < P0 + R) ? cur[zo + (hy0 + oy) * G0 + hxa] : 0.0f;
-        h[1] = (y0ok && lx < 2 * R && hxb < P0 + R) ? cur[zo + (hy0 + oy) * G0 + hxb] : 0.0f;
-        h[2] = (y1ok && hxa < P0 + R) ? cur[zo + (hy1 + oy) * G0 + hxa] : 0.0f;
-        h[3] = (y1ok && lx < 2 * R && hxb < P0 + R) ? cur[zo + (hy1 + oy) * G0 + hxb] : 0.0f;
-        h[4] = (lx < 2 * R && ya < P1 + R && hxc < P0 + R) ? cur[zo + (ya + oy) * G0 + hxc] : 0.0f;
-        h[5] = (lx < 2 * R && yb < P1 + R && hxc < P0 + R) ? cur[zo + (yb + oy) * G0 + hxc] : 0.0f;
+        h[0] = (y0ok && xaok) ? cur[zo + (hy0 + oy) * G0 + hxa] : 0.0f;
+        h[1] = (y0ok && xbok) ? cur[zo + (hy0 + oy) * G0 + hxb] : 0.0f;
+        h[2] = (y1ok && xaok) ? cur[zo + (hy1 + oy) * G0 + hxa] : 0.0f;
+        h[3] = (y1ok && xbok) ? cur[zo + (hy1 + oy) * G0 + hxb] : 0.0f;
+        h[4] = (xcok && ya < P1) ? cur[zo + (ya + oy) * G0 + hxc] : 0.0f;
+        h[5] = (xcok && yb < P1) ? cur[zo + (yb + oy) * G0 + hxc] : 0.0f;
     };
 
     float qa[2 * R + 1], qb[2 * R + 1];
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) {
         const int z = zc0 - R + i;
-        const bool zin = z < P2 + R;
+        const bool zin = z >= 0 && z < P2;
         qa[i] = (ca && zin) ? cur[(z + R) * PL + cola] : 0.0f;
         qb[i] = (cb && zin) ? cur[(z + R) * PL + colb] : 0.0f;
     }
     float h[6];
     load_halo(zc0, h);
-    const float hxy_a = layer_frac2(x, L.n[0], L.nb, ph.inv_nb) + layer_frac2(ya, L.n[1], L.nb, ph.inv_nb);
-    const float hxy_b = layer_frac2(x, L.n[0], L.nb, ph.inv_nb) + layer_frac2(yb, L.n[1], L.nb, ph.inv_nb);
+    const float hx = layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
+    const float hxy_a = hx + layer_frac2(ya, (int)L.n[1], L.nb, ph.inv_nb);
+    const float hxy_b = hx + layer_frac2(yb, (int)L.n[1], L.nb, ph.inv_nb);
 
     for (int lz = 0; lz < T3Z; ++lz) {
         const int z = zc0 + lz;
         if (z >= P2) break;
         const int zo = (z + R) * PL;
-        qa[2 * R] = ca ? cur[zo + R * PL + cola] : 0.0f;   // z + R < P2 + R always
-        qb[2 * R] = cb ? cur[zo + R * PL + colb] : 0.0f;
+        const bool zr = z + R < P2;
+        qa[2 * R] = (ca && zr) ? cur[zo + R * PL + cola] : 0.0f;
+        qb[2 * R] = (cb && zr) ? cur[zo + R * PL + colb] : 0.0f;
         const float pa = oa ? prev[zo + cola] : 0.0f, pb = ob ? prev[zo + colb] : 0.0f;
         const float ba = oa ? beta[zo + cola] : 0.0f, bb = ob ? beta[zo + colb] : 0.0f;
 
@@ -257,23 +265,23 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
             pt[R + ly][hc] = h[4];
             pt[R + 4 + ly][hc] = h[5];
         }
-        int sb = 0, se = 0;
+        float sa = 0.0f, sbv = 0.0f;   // point-source terms of this thread's two nodes
         if (a.inject) {
             const int64_t tile_id = (((int64_t)shot * L.ntiles[2] + z) * nty + by) * ntx + bx;
-            sb = a.inj.tile_ptr[tile_id];
-            se = a.inj.tile_ptr[tile_id + 1];
-        }
-        const bool has_src = sb < se;
-        float *srcs = srcs2[lz & 1];
-        if (has_src) {
-            srcs[tid] = 0.0f;
-            srcs[tid + 256] = 0.0f;
+            const int s0 = a.inj.tile_ptr[tile_id], s1 = a.inj.tile_ptr[tile_id + 1];
+            if (s0 < s1) {
+                const float *amp = a.amp.ptr + shot * a.amp.shot_stride + (int64_t)a.k * a.amp.k_stride;
+                for (int sg = s0; sg < s1; ++sg) {
+                    const int loc = a.inj.seg_local[sg];      // ly * 64 + lx within the plane tile
+                    const float v = segment_value(a.inj, amp, a.amp.scale, sg);
+                    if ((loc & 63) == lx) {
+                        if ((loc >> 6) == ly) sa += v;
+                        if ((loc >> 6) == ly + 4) sbv += v;
+                    }
+                }
+            }
         }
         __syncthreads();
-        if (has_src) {
-            gather_sources(a.inj, a.amp, shot, a.k, sb, se, srcs);
-            __syncthreads();
-        }
         if (z + 1 < P2 && lz + 1 < T3Z) load_halo(z + 1, h);   // prefetch, overlaps the compute below
 
         float lapa = 3.0f * ph.c[0] * qa[R], lapb = 3.0f * ph.c[0] * qb[R];
@@ -284,15 +292,9 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
             lapb += ph.c[k] * ((pt[R + 4 + ly][R + lx - k] + pt[R + 4 + ly][R + lx + k]) +
                                (pt[R + 4 + ly - k][R + lx] + pt[R + 4 + ly + k][R + lx]) + (qb[R - k] + qb[R + k]));
         }
-        const float hz = layer_frac2(z, L.n[2], L.nb, ph.inv_nb);
-        if (oa) {
-            const float s = has_src ? srcs[ly * T3X + lx] : 0.0f;
-            next[zo + cola] = leapfrog(qa[R], pa, ba, lapa, s, ph.hd_max * (hxy_a + hz));
-        }
-        if (ob) {
-            const float s = has_src ? srcs[(ly + 4) * T3X + lx] : 0.0f;
-            next[zo + colb] = leapfrog(qb[R], pb, bb, lapb, s, ph.hd_max * (hxy_b + hz));
-        }
+        const float hz = layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb);
+        if (oa) next[zo + cola] = leapfrog(qa[R], pa, ba, lapa, sa, ph.hd_max * (hxy_a + hz));
+        if (ob) next[zo + colb] = leapfrog(qb[R], pb, bb, lapb, sbv, ph.hd_max * (hxy_b + hz));
 #pragma unroll
         for (int i = 0; i < 2 * R; ++i) {
             qa[i] = qa[i + 1];
@@ -461,19 +463,22 @@ struct PointIndex {
     bool ok;
 };
 
-// Block = 64 (x) by 4 (rows of [z][y]); grid (x chunks, row chunks, shots).
+// Block = 256 consecutive physical points of one shot (so every buffered
+// slot is read in runs of about 1 KB); grid (point chunks, shots).
 __device__ __forceinline__ PointIndex point_index(const Layout &L) {
     PointIndex pi;
-    const int x = (int)blockIdx.x * 64 + (int)(threadIdx.x & 63);
-    const int row = (int)blockIdx.y * 4 + (int)(threadIdx.x >> 6);
-    const int n0 = (int)L.n[0], n1 = (int)L.n[1], rows = (int)(L.n[1] * L.n[2]);
-    pi.ok = x < n0 && row < rows;
+    const int p = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    pi.ok = p < L.nphys;
+    const int n0 = (int)L.n[0], n1 = (int)L.n[1];
+    const int row = p / n0, x = p - row * n0;
     const int z = row / n1, y = row - z * n1;
     const int oyb = L.ndim == 3 ? L.nb : 0;
     pi.off = (int)L.pad_off(x + L.nb, y + oyb, z + L.nb);
-    pi.p = (int64_t)row * n0 + x;
+    pi.p = p;
     return pi;
 }
+
+constexpr int kAccUnroll = 8;   // buffered steps whose loads are issued together
 
 template <int RC>
 __global__ __launch_bounds__(256) void k_accum_fwd(const Layout L, const float *__restrict__ ring, int nslots,
@@ -481,28 +486,58 @@ __global__ __launch_bounds__(256) void k_accum_fwd(const Layout L, const float *
                                                    float *__restrict__ ubar) {
     const PointIndex pi = point_index(L);
     if (!pi.ok) return;
-    const int shot = blockIdx.z;
+    const int shot = blockIdx.y;
     const float *base = ring + shot * L.shot_floats + pi.off;
     for (int j0 = 0; j0 < r; j0 += RC) {
         const int rc = (r - j0) < RC ? (r - j0) : RC;
         float acc[RC];
 #pragma unroll
         for (int j = 0; j < RC; ++j) acc[j] = 0.0f;
-        int slot = s_lo % nslots;
-#pragma unroll 4
-        for (int s = s_lo; s <= s_hi; ++s) {
-            const float v = base[(int64_t)slot * L.slot_floats];
+        int s = s_lo;
+        for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
+            float v[kAccUnroll];
+#pragma unroll
+            for (int u = 0; u < kAccUnroll; ++u) v[u] = base[(int64_t)((s + u) % nslots) * L.slot_floats];
+#pragma unroll
+            for (int u = 0; u < kAccUnroll; ++u) {
+                const float *zr = Z + ((int64_t)shot * nt + s + u) * r + j0;
+#pragma unroll
+                for (int j = 0; j < RC; ++j)
+                    if (j < rc) acc[j] = fmaf(zr[j], v[u], acc[j]);
+            }
+        }
+        for (; s <= s_hi; ++s) {
+            const float v = base[(int64_t)(s % nslots) * L.slot_floats];
             const float *zr = Z + ((int64_t)shot * nt + s) * r + j0;
 #pragma unroll
             for (int j = 0; j < RC; ++j)
                 if (j < rc) acc[j] = fmaf(zr[j], v, acc[j]);
-            slot = slot + 1 == nslots ? 0 : slot + 1;
         }
         float *ub = ubar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
 #pragma unroll
         for (int j = 0; j < RC; ++j)
             if (j < rc) ub[(int64_t)j * L.nphys] += acc[j];
     }
+}
+
+// One buffered step of the adjoint contraction: w = lam^{s-1} - 2 lam^s + lam^{s+1}.
+template <int RC, int FOLD>
+__device__ __forceinline__ void adj_step(float &lm, float &l0, float lp, const float *zr, int rc, const float *u,
+                                         float *acc, float &fsum) {
+    const float w = (lm - 2.0f * l0) + lp;
+    if (FOLD) {
+        float t = 0.0f;
+#pragma unroll
+        for (int j = 0; j < RC; ++j)
+            if (j < rc) t = fmaf(zr[j], u[j], t);
+        fsum = fmaf(w, t, fsum);
+    } else {
+#pragma unroll
+        for (int j = 0; j < RC; ++j)
+            if (j < rc) acc[j] = fmaf(zr[j], w, acc[j]);
+    }
+    lm = l0;
+    l0 = lp;
 }
 
 template <int RC, int FOLD>
@@ -512,7 +547,7 @@ __global__ __launch_bounds__(256) void k_accum_adj(const Layout L, const float *
                                                    float *__restrict__ vbar, float *__restrict__ gpart) {
     const PointIndex pi = point_index(L);
     if (!pi.ok) return;
-    const int shot = blockIdx.z;
+    const int shot = blockIdx.y;
     const float *base = ring + shot * L.shot_floats + pi.off;
     float gacc = 0.0f;
     for (int j0 = 0; j0 < r; j0 += RC) {
@@ -530,32 +565,21 @@ __global__ __launch_bounds__(256) void k_accum_adj(const Layout L, const float *
             for (int j = 0; j < RC; ++j)
                 if (j < rc) u[j] = ub[(int64_t)j * L.nphys];
         }
-        int slot = (s_lo - 1) % nslots;
-        float lm = base[(int64_t)slot * L.slot_floats];
-        slot = slot + 1 == nslots ? 0 : slot + 1;
-        float l0 = base[(int64_t)slot * L.slot_floats];
-        slot = slot + 1 == nslots ? 0 : slot + 1;
+        float lm = base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats];
+        float l0 = base[(int64_t)(s_lo % nslots) * L.slot_floats];
         float fsum = 0.0f;
-#pragma unroll 4
-        for (int s = s_lo; s <= s_hi; ++s) {
-            const float lp = base[(int64_t)slot * L.slot_floats];
-            slot = slot + 1 == nslots ? 0 : slot + 1;
-            const float w = (lm - 2.0f * l0) + lp;
-            const float *zr = Z + ((int64_t)shot * nt + s) * r + j0;
-            if (FOLD) {
-                float t = 0.0f;
+        int s = s_lo;
+        for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
+            float lp[kAccUnroll];
 #pragma unroll
-                for (int j = 0; j < RC; ++j)
-                    if (j < rc) t = fmaf(zr[j], u[j], t);
-                fsum = fmaf(w, t, fsum);
-            } else {
+            for (int q = 0; q < kAccUnroll; ++q) lp[q] = base[(int64_t)((s + q + 1) % nslots) * L.slot_floats];
 #pragma unroll
-                for (int j = 0; j < RC; ++j)
-                    if (j < rc) acc[j] = fmaf(zr[j], w, acc[j]);
-            }
-            lm = l0;
-            l0 = lp;
+            for (int q = 0; q < kAccUnroll; ++q)
+                adj_step<RC, FOLD>(lm, l0, lp[q], Z + ((int64_t)shot * nt + s + q) * r + j0, rc, u, acc, fsum);
         }
+        for (; s <= s_hi; ++s)
+            adj_step<RC, FOLD>(lm, l0, base[(int64_t)((s + 1) % nslots) * L.slot_floats],
+                               Z + ((int64_t)shot * nt + s) * r + j0, rc, u, acc, fsum);
         if (FOLD) {
             gacc += fsum;
         } else {
@@ -573,19 +597,30 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
                                                     float *__restrict__ gpart) {
     const PointIndex pi = point_index(L);
     if (!pi.ok) return;
-    const int shot = blockIdx.z;
+    const int shot = blockIdx.y;
     const float *hb = hist + shot * L.shot_floats + pi.off;
     const float *base = ring + shot * L.shot_floats + pi.off;
-    int slot = (s_lo - 1) % nslots;
-    float lm = base[(int64_t)slot * L.slot_floats];
-    slot = slot + 1 == nslots ? 0 : slot + 1;
-    float l0 = base[(int64_t)slot * L.slot_floats];
-    slot = slot + 1 == nslots ? 0 : slot + 1;
+    float lm = base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats];
+    float l0 = base[(int64_t)(s_lo % nslots) * L.slot_floats];
     float acc = 0.0f;
-#pragma unroll 4
-    for (int s = s_lo; s <= s_hi; ++s) {
-        const float lp = base[(int64_t)slot * L.slot_floats];
-        slot = slot + 1 == nslots ? 0 : slot + 1;
+    int s = s_lo;
+    for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
+        float lp[kAccUnroll], uh[kAccUnroll];
+#pragma unroll
+        for (int q = 0; q < kAccUnroll; ++q) {
+            lp[q] = base[(int64_t)((s + q + 1) % nslots) * L.slot_floats];
+            uh[q] = hb[(int64_t)(s + q) * L.slot_floats];
+        }
+#pragma unroll
+        for (int q = 0; q < kAccUnroll; ++q) {
+            const float w = (lm - 2.0f * l0) + lp[q];
+            acc = fmaf(uh[q], w, acc);
+            lm = l0;
+            l0 = lp[q];
+        }
+    }
+    for (; s <= s_hi; ++s) {
+        const float lp = base[(int64_t)((s + 1) % nslots) * L.slot_floats];
         const float w = (lm - 2.0f * l0) + lp;
         acc = fmaf(hb[(int64_t)s * L.slot_floats], w, acc);
         lm = l0;
@@ -595,7 +630,7 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
 }
 
 static dim3 point_grid(const Layout &L) {
-    return dim3((unsigned)((L.n[0] + 63) / 64), (unsigned)((L.n[1] * L.n[2] + 3) / 4), (unsigned)L.S);
+    return dim3((unsigned)((L.nphys + 255) / 256), (unsigned)L.S);
 }
 
 hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,

@@ -370,7 +370,7 @@ tpx_status build_tables(const Problem &P, const tpx_grid *g, const tpx_geom *geo
 // write costs 8 r / b bytes per point-step, the ring costs (b + 2) slots.
 int default_block(const Layout &L, int nt) {
     const double slot_bytes = (double)L.slot_floats * 4.0;
-    const double cap = 24e9;
+    const double cap = 48e9;
     int b = 128;
     while (b > 16 && (b + 2) * slot_bytes > cap) b /= 2;
     if (b > nt - 1) b = nt - 1;
@@ -523,7 +523,9 @@ tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, cons
     const int nt = C.P.nt;
     float *buf = hist ? hist : C.ring;
     const int ns = hist ? nt : C.plan.nslots;
-    TPX_HIP(launch_fill_zero(hist ? (void *)hist : (void *)C.ring, (size_t)L.slot_floats * 4 * ns, C.stream));
+    // u^{-1} = u^0 = 0: the first step reads slot 0 as both levels.  Other
+    // slots are written before they are read, and ghost cells are never read.
+    TPX_HIP(launch_fill_zero(slot_ptr(buf, L, ns, 0), (size_t)L.slot_floats * 4, C.stream));
     if (ubar) TPX_HIP(launch_fill_zero(ubar, align_up((size_t)L.S * r * L.nphys * 4), C.stream));
     StepArgs a;
     memset(&a, 0, sizeof a);
@@ -578,7 +580,9 @@ tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
     const Layout &L = C.P.L;
     const int nt = C.P.nt;
     const int ns = C.plan.nslots;
-    TPX_HIP(launch_fill_zero(C.ring, (size_t)L.slot_floats * 4 * ns, C.stream));
+    // lambda^{nt} = lambda^{nt-1} = 0; every other slot is written before it is read
+    TPX_HIP(launch_fill_zero(slot_ptr(C.ring, L, ns, nt), (size_t)L.slot_floats * 4, C.stream));
+    TPX_HIP(launch_fill_zero(slot_ptr(C.ring, L, ns, nt - 1), (size_t)L.slot_floats * 4, C.stream));
     if (o.gpart) TPX_HIP(launch_fill_zero(o.gpart, align_up((size_t)L.S * L.nphys * 4), C.stream));
     if (o.vbar) TPX_HIP(launch_fill_zero(o.vbar, align_up((size_t)L.S * o.r * L.nphys * 4), C.stream));
     StepArgs a;

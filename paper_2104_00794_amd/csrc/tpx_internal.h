@@ -23,9 +23,9 @@ namespace tpx {
 // ---------------------------------------------------------------------------
 constexpr int XO = 32;
 
-// 2D step kernel tile: 64 (x) by 16 (z) outputs, 256 threads.
+// 2D step kernel tile: 64 (x) by 32 (z) outputs, 256 threads.
 constexpr int T2X = 64;
-constexpr int T2Z = 16;
+constexpr int T2Z = 32;
 // 3D step kernel tile: 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
 constexpr int T3Y = 8;
