@@ -167,6 +167,24 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
                                const float *m, const float *grad_d, const void *state, size_t state_bytes,
                                float *g, void *ws, size_t ws_bytes, void *stream);
 
+/* Resumable probed-gradient job, for servers that interleave several
+ * gradients on one GPU.  tpx_job_create validates, uploads the geometry tables
+ * and enqueues the set-up work on `stream`; each tpx_job_advance enqueues at
+ * most `max_steps` further time steps (plus the probe contractions, residual
+ * and imaging that fall due) and sets *finished once everything is enqueued.
+ * The outputs g, J (and d_out) are valid when the stream has executed the last
+ * advance.  m, d_obs, g, J, d_out and ws must stay allocated until then, and
+ * successive calls of one job must be ordered on the device (the same stream,
+ * or streams joined by events).  Jobs with separate workspaces are
+ * independent: a job's results do not depend on what runs beside it. */
+typedef struct tpx_job tpx_job;
+tpx_status tpx_job_create(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
+                          const float *d_obs, float *g, double *J, float *d_out, void *ws, size_t ws_bytes,
+                          void *stream, tpx_job **job);
+tpx_status tpx_job_advance(tpx_job *job, int32_t max_steps, void *stream, int32_t *finished);
+tpx_status tpx_job_progress(const tpx_job *job, int64_t *steps_done, int64_t *steps_total);
+void tpx_job_destroy(tpx_job *job);
+
 /* Device-side checks of the last call that used `ws`, after waiting for
  * `stream`: TPX_E_NUMERIC if the model held a non-finite or non-positive
  * value, TPX_E_CFL if it held a velocity above damp_vmax. */

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -518,16 +519,37 @@ float *slot_ptr(float *base, const Layout &L, int nslots, int k) {
 // Forward propagation over k = 0..nt-2 in the ring (or the history when
 // `hist` is set), sampling traces into d.  When `Z` is set, the probed
 // wavefield ubar_j += Z[s,j] u^s is accumulated every `block` steps.
-tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, const float *Z, int r, float *ubar) {
+// The loop is resumable: fwd_advance runs at most `max_steps` steps per call.
+struct FwdLoop {
+    StepArgs a;
+    SampleTables smp;
+    float *buf = nullptr;
+    int ns = 0;
+    const float *Z = nullptr;
+    int r = 0;
+    float *ubar = nullptr;
+    int k = 0;
+    int s_lo = 1;
+    bool finished = false;
+};
+
+tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
+                     float *ubar) {
     const Layout &L = C.P.L;
     const int nt = C.P.nt;
-    float *buf = hist ? hist : C.ring;
-    const int ns = hist ? nt : C.plan.nslots;
+    f.buf = hist ? hist : C.ring;
+    f.ns = hist ? nt : C.plan.nslots;
+    f.Z = Z;
+    f.r = r;
+    f.ubar = ubar;
+    f.k = 0;
+    f.s_lo = 1;
+    f.finished = false;
     // u^{-1} = u^0 = 0: the first step reads slot 0 as both levels.  Other
     // slots are written before they are read, and ghost cells are never read.
-    TPX_HIP(launch_fill_zero(slot_ptr(buf, L, ns, 0), (size_t)L.slot_floats * 4, C.stream));
+    TPX_HIP(launch_fill_zero(slot_ptr(f.buf, L, f.ns, 0), (size_t)L.slot_floats * 4, C.stream));
     if (ubar) TPX_HIP(launch_fill_zero(ubar, align_up((size_t)L.S * r * L.nphys * 4), C.stream));
-    StepArgs a;
+    StepArgs &a = f.a;
     memset(&a, 0, sizeof a);
     a.beta = C.beta;
     a.inject = 1;
@@ -536,29 +558,49 @@ tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, cons
     a.amp.shot_stride = nt;
     a.amp.k_stride = 1;
     a.amp.scale = 1.0f;
-    SampleTables smp = C.rec_smp;
-    smp.out = d;
-    smp.out_shot_stride = (int64_t)nt * C.P.nrec;
-    smp.out_k_stride = C.P.nrec;
-    smp.scale = 1.0f;
-    a.do_sample = (d && smp.nsmp > 0) ? 1 : 0;
-    a.smp = smp;
-    int s_lo = 1;
-    for (int k = 0; k <= nt - 2; ++k) {
+    f.smp = C.rec_smp;
+    f.smp.out = d;
+    f.smp.out_shot_stride = (int64_t)nt * C.P.nrec;
+    f.smp.out_k_stride = C.P.nrec;
+    f.smp.scale = 1.0f;
+    a.do_sample = (d && f.smp.nsmp > 0) ? 1 : 0;
+    a.smp = f.smp;
+    return TPX_OK;
+}
+
+tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
+    const Layout &L = C.P.L;
+    const int nt = C.P.nt;
+    StepArgs &a = f.a;
+    int64_t n = 0;
+    for (; f.k <= nt - 2 && n < max_steps; ++f.k, ++n) {
+        const int k = f.k;
         a.k = k;
-        a.cur = slot_ptr(buf, L, ns, k);
-        a.prev = k == 0 ? a.cur : slot_ptr(buf, L, ns, k - 1);  // u^{-1} = u^0 = 0
-        a.next = slot_ptr(buf, L, ns, k + 1);
+        a.cur = slot_ptr(f.buf, L, f.ns, k);
+        a.prev = k == 0 ? a.cur : slot_ptr(f.buf, L, f.ns, k - 1);  // u^{-1} = u^0 = 0
+        a.next = slot_ptr(f.buf, L, f.ns, k + 1);
         TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
         const int s = k + 1;
-        if (Z && (s - s_lo + 1 == C.plan.block || s == nt - 1)) {
+        if (f.Z && (s - f.s_lo + 1 == C.plan.block || s == nt - 1)) {
+            const int s_lo = f.s_lo;
             TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream,
-                         [&] { return launch_accum_fwd(L, buf, ns, s_lo, s, Z, nt, r, ubar, C.stream); }));
-            s_lo = s + 1;
+                         [&] { return launch_accum_fwd(L, f.buf, f.ns, s_lo, s, f.Z, nt, f.r, f.ubar, C.stream); }));
+            f.s_lo = s + 1;
         }
     }
-    if (a.do_sample) TPX_HIP(launch_sample_only(L, slot_ptr(buf, L, ns, nt - 1), nt - 1, smp, C.stream));
+    if (f.k > nt - 2 && !f.finished) {
+        if (a.do_sample) TPX_HIP(launch_sample_only(L, slot_ptr(f.buf, L, f.ns, nt - 1), nt - 1, f.smp, C.stream));
+        f.finished = true;
+    }
+    if (used) *used = n;
     return TPX_OK;
+}
+
+tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, const float *Z, int r, float *ubar) {
+    FwdLoop f;
+    tpx_status st = fwd_begin(C, f, wavelet, d, hist, Z, r, ubar);
+    if (st != TPX_OK) return st;
+    return fwd_advance(C, f, INT64_MAX, nullptr);
 }
 
 // Adjoint propagation k = nt-1..1 injecting amp/dt^2 at the receivers.
@@ -576,16 +618,29 @@ struct AdjOut {
     const float *hist = nullptr;
 };
 
-tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
+struct AdjLoop {
+    StepArgs a;
+    SampleTables smp;
+    AdjOut o;
+    int k = 0;
+    int s_hi = 0;
+    bool finished = false;
+};
+
+tpx_status adj_begin(Ctx &C, AdjLoop &b, const float *amp, const AdjOut &o) {
     const Layout &L = C.P.L;
     const int nt = C.P.nt;
     const int ns = C.plan.nslots;
+    b.o = o;
+    b.k = nt - 1;
+    b.s_hi = nt - 1;
+    b.finished = false;
     // lambda^{nt} = lambda^{nt-1} = 0; every other slot is written before it is read
     TPX_HIP(launch_fill_zero(slot_ptr(C.ring, L, ns, nt), (size_t)L.slot_floats * 4, C.stream));
     TPX_HIP(launch_fill_zero(slot_ptr(C.ring, L, ns, nt - 1), (size_t)L.slot_floats * 4, C.stream));
     if (o.gpart) TPX_HIP(launch_fill_zero(o.gpart, align_up((size_t)L.S * L.nphys * 4), C.stream));
     if (o.vbar) TPX_HIP(launch_fill_zero(o.vbar, align_up((size_t)L.S * o.r * L.nphys * 4), C.stream));
-    StepArgs a;
+    StepArgs &a = b.a;
     memset(&a, 0, sizeof a);
     a.beta = C.beta;
     a.inject = C.P.nrec > 0 ? 1 : 0;
@@ -594,23 +649,34 @@ tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
     a.amp.shot_stride = (int64_t)nt * C.P.nrec;
     a.amp.k_stride = C.P.nrec;
     a.amp.scale = (float)(1.0 / (C.P.dt * C.P.dt));
-    SampleTables smp = C.src_smp;
-    smp.out = o.q_adj;
-    smp.out_shot_stride = nt;
-    smp.out_k_stride = 1;
-    smp.scale = (float)(C.P.dt * C.P.dt);
+    b.smp = C.src_smp;
+    b.smp.out = o.q_adj;
+    b.smp.out_shot_stride = nt;
+    b.smp.out_k_stride = 1;
+    b.smp.scale = (float)(C.P.dt * C.P.dt);
     a.do_sample = o.q_adj ? 1 : 0;
-    a.smp = smp;
+    a.smp = b.smp;
+    return TPX_OK;
+}
+
+tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
+    const Layout &L = C.P.L;
+    const int nt = C.P.nt;
+    const int ns = C.plan.nslots;
+    const AdjOut &o = b.o;
+    StepArgs &a = b.a;
     const bool accum = o.Z || o.hist;
-    int s_hi = nt - 1;
-    for (int k = nt - 1; k >= 1; --k) {
+    int64_t n = 0;
+    for (; b.k >= 1 && n < max_steps; --b.k, ++n) {
+        const int k = b.k;
         a.k = k;
         a.cur = slot_ptr(C.ring, L, ns, k);
         a.prev = slot_ptr(C.ring, L, ns, k + 1);
         a.next = slot_ptr(C.ring, L, ns, k - 1);
         TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
         // lambda^{k-1} is known: w^k can be formed
-        if (accum && (s_hi - k + 1 == C.plan.block || k == 1)) {
+        if (accum && (b.s_hi - k + 1 == C.plan.block || k == 1)) {
+            const int s_hi = b.s_hi;
             if (o.hist)
                 TPX_HIP(prof(TPX_KERNEL_ACCUM_FULL, C.stream,
                              [&] { return launch_accum_full(L, o.hist, C.ring, ns, k, s_hi, o.gpart, C.stream); }));
@@ -619,11 +685,22 @@ tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
                     return launch_accum_adj(L, C.ring, ns, k, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c, o.vbar,
                                             o.gpart, C.stream);
                 }));
-            s_hi = k - 1;
+            b.s_hi = k - 1;
         }
     }
-    if (o.q_adj) TPX_HIP(launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, smp, C.stream));
+    if (b.k < 1 && !b.finished) {
+        if (o.q_adj) TPX_HIP(launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, b.smp, C.stream));
+        b.finished = true;
+    }
+    if (used) *used = n;
     return TPX_OK;
+}
+
+tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
+    AdjLoop b;
+    tpx_status st = adj_begin(C, b, amp, o);
+    if (st != TPX_OK) return st;
+    return adj_advance(C, b, INT64_MAX, nullptr);
 }
 
 const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, tpx_status *st) {
@@ -652,6 +729,91 @@ Mode mode_of(int32_t call, bool *ok) {
     case TPX_CALL_BACKWARD_PROBED: return M_BWD_PROBED;
     default: *ok = false; return M_FORWARD;
     }
+}
+
+// A probed-gradient job that can be advanced a bounded number of time steps
+// at a time (forward with probing, residual/objective, adjoint with probing,
+// imaging).  tpx_gradient_probed runs one to the end; a server interleaves
+// several.
+struct GradJob {
+    Ctx C;
+    tpx_probe probe;
+    const float *wavelet = nullptr;
+    const float *d_obs = nullptr;
+    float *g = nullptr;
+    double *J = nullptr;
+    float *d = nullptr;
+    float *res = nullptr;
+    const float *Z = nullptr;
+    float *ubar = nullptr;
+    FwdLoop f;
+    AdjLoop b;
+    int phase = 0;  // 0 forward, 1 adjoint, 2 done
+    int64_t done_steps = 0, total_steps = 0;
+};
+
+tpx_status job_init(GradJob &J, const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
+                    const float *d_obs, float *g, double *Jout, float *d_out, void *ws, size_t ws_bytes,
+                    void *stream) {
+    if ((!d_obs && geom && geom->nrec > 0) || !g || !Jout)
+        return fail(TPX_E_INVAL, "d_obs, g and J must not be NULL");
+    tpx_status st = setup(J.C, grid, geom, probe, M_GRAD_PROBED, m, ws, ws_bytes, stream);
+    if (st != TPX_OK) return st;
+    J.probe = *probe;
+    J.wavelet = geom->wavelet;
+    J.d_obs = d_obs;
+    J.g = g;
+    J.J = Jout;
+    J.d = d_out ? d_out : (float *)(J.C.ws + J.C.plan.d);
+    J.res = (float *)(J.C.ws + J.C.plan.res);
+    J.ubar = (float *)(J.C.ws + J.C.plan.ubar);
+    J.Z = probe_matrix_dev(J.C, probe, &st);
+    if (st != TPX_OK) return st;
+    st = fwd_begin(J.C, J.f, J.wavelet, J.d, nullptr, J.Z, probe->r, J.ubar);
+    if (st != TPX_OK) return st;
+    J.phase = 0;
+    J.done_steps = 0;
+    J.total_steps = 2 * (int64_t)(J.C.P.nt - 1);
+    return TPX_OK;
+}
+
+tpx_status job_advance(GradJob &J, int64_t max_steps) {
+    int64_t budget = max_steps;
+    tpx_status st;
+    if (J.phase == 0) {
+        int64_t used = 0;
+        if ((st = fwd_advance(J.C, J.f, budget, &used)) != TPX_OK) return st;
+        budget -= used;
+        J.done_steps += used;
+        if (J.f.finished) {
+            const Layout &L = J.C.P.L;
+            const int64_t ntr = (int64_t)L.S * J.C.P.nt * J.C.P.nrec;
+            TPX_HIP(launch_residual(J.d, J.d_obs, J.res, ntr, (double *)(J.C.ws + J.C.plan.parts),
+                                    residual_parts(ntr), J.J, J.C.stream));
+            AdjOut o;
+            o.Z = J.Z;
+            o.r = J.probe.r;
+            o.fold = J.probe.keep_vbar ? 0 : 1;
+            o.ubar = J.ubar;
+            o.c = probe_scale(&J.probe);
+            o.vbar = J.probe.keep_vbar ? (float *)(J.C.ws + J.C.plan.vbar) : nullptr;
+            o.gpart = J.probe.keep_vbar ? nullptr : (float *)(J.C.ws + J.C.plan.gpart);
+            if ((st = adj_begin(J.C, J.b, J.res, o)) != TPX_OK) return st;
+            J.phase = 1;
+        }
+    }
+    if (J.phase == 1 && budget > 0) {
+        int64_t used = 0;
+        if ((st = adj_advance(J.C, J.b, budget, &used)) != TPX_OK) return st;
+        J.done_steps += used;
+        if (J.b.finished) {
+            const Layout &L = J.C.P.L;
+            if (J.probe.keep_vbar) TPX_HIP(launch_image_probed(L, J.probe.r, J.b.o.c, J.ubar, J.b.o.vbar, J.g, J.C.stream));
+            else TPX_HIP(launch_image_sum(L, J.b.o.gpart, J.g, J.C.stream));
+            J.phase = 2;
+        }
+    }
+    return TPX_OK;
 }
 
 template <class F>
@@ -730,36 +892,52 @@ tpx_status tpx_gradient_probed(const tpx_grid *grid, const tpx_geom *geom, const
                                const float *d_obs, float *g, double *J, float *d_out, void *ws, size_t ws_bytes,
                                void *stream) {
     return guarded([&]() -> tpx_status {
-        if ((!d_obs && geom && geom->nrec > 0) || !g || !J) return fail(TPX_E_INVAL, "d_obs, g and J must not be NULL");
-        Ctx C;
-        tpx_status st = setup(C, grid, geom, probe, M_GRAD_PROBED, m, ws, ws_bytes, stream);
+        GradJob job;
+        tpx_status st = job_init(job, grid, geom, probe, m, d_obs, g, J, d_out, ws, ws_bytes, stream);
         if (st != TPX_OK) return st;
-        const Layout &L = C.P.L;
-        const float *Z = probe_matrix_dev(C, probe, &st);
-        if (st != TPX_OK) return st;
-        float *ubar = (float *)(C.ws + C.plan.ubar);
-        float *d = d_out ? d_out : (float *)(C.ws + C.plan.d);
-        float *res = (float *)(C.ws + C.plan.res);
-        st = run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, ubar);
-        if (st != TPX_OK) return st;
-        const int64_t ntr = (int64_t)L.S * C.P.nt * C.P.nrec;
-        const int parts = residual_parts(ntr);
-        TPX_HIP(launch_residual(d, d_obs, res, ntr, (double *)(C.ws + C.plan.parts), parts, J, C.stream));
-        AdjOut o;
-        o.Z = Z;
-        o.r = probe->r;
-        o.fold = probe->keep_vbar ? 0 : 1;
-        o.ubar = ubar;
-        o.c = probe_scale(probe);
-        o.vbar = probe->keep_vbar ? (float *)(C.ws + C.plan.vbar) : nullptr;
-        o.gpart = probe->keep_vbar ? nullptr : (float *)(C.ws + C.plan.gpart);
-        st = run_adjoint(C, res, o);
-        if (st != TPX_OK) return st;
-        if (probe->keep_vbar) TPX_HIP(launch_image_probed(L, probe->r, o.c, ubar, o.vbar, g, C.stream));
-        else TPX_HIP(launch_image_sum(L, o.gpart, g, C.stream));
+        return job_advance(job, INT64_MAX);
+    });
+}
+
+struct tpx_job {
+    GradJob j;
+};
+
+tpx_status tpx_job_create(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
+                          const float *d_obs, float *g, double *J, float *d_out, void *ws, size_t ws_bytes,
+                          void *stream, tpx_job **job) {
+    return guarded([&]() -> tpx_status {
+        if (!job) return fail(TPX_E_INVAL, "job must not be NULL");
+        *job = nullptr;
+        tpx_job *p = new tpx_job();
+        tpx_status st = job_init(p->j, grid, geom, probe, m, d_obs, g, J, d_out, ws, ws_bytes, stream);
+        if (st != TPX_OK) {
+            delete p;
+            return st;
+        }
+        *job = p;
         return TPX_OK;
     });
 }
+
+tpx_status tpx_job_advance(tpx_job *job, int32_t max_steps, void *stream, int32_t *finished) {
+    return guarded([&]() -> tpx_status {
+        if (!job || max_steps < 1) return fail(TPX_E_INVAL, "job must not be NULL and max_steps >= 1");
+        job->j.C.stream = (hipStream_t)stream;
+        tpx_status st = job_advance(job->j, max_steps);
+        if (finished) *finished = job->j.phase == 2 ? 1 : 0;
+        return st;
+    });
+}
+
+tpx_status tpx_job_progress(const tpx_job *job, int64_t *steps_done, int64_t *steps_total) {
+    if (!job || !steps_done || !steps_total) return fail(TPX_E_INVAL, "NULL argument");
+    *steps_done = job->j.done_steps;
+    *steps_total = job->j.total_steps;
+    return TPX_OK;
+}
+
+void tpx_job_destroy(tpx_job *job) { delete job; }
 
 tpx_status tpx_gradient_full(const tpx_grid *grid, const tpx_geom *geom, const float *m, const float *d_obs, float *g,
                              double *J, float *d_out, void *ws, size_t ws_bytes, void *stream) {

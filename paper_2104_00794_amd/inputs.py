@@ -258,3 +258,52 @@ def small_3d(nz=20, ny=22, nx=24, h=10.0, order=8, nt=90, nbl=5, nshots=1, nrec=
             float(rng.uniform(0.05, 0.2) * Zd)) for _ in range(nrec)]
     return Workload("small_3d", (nz, ny, nx), h, order, dt, nt, f_khz, 1.5, vmax, nbl=nbl, r=r,
                     probe_seed=seed + 100, model_seed=seed, smooth_sigma=2.0, src=src, rec=rec)
+
+
+# --------------------------------------------------------------------------- #
+# serving mix
+# --------------------------------------------------------------------------- #
+
+SERVING_SHAPES = (
+    ((201, 201), 10.0),
+    ((201, 401), 10.0),
+    ((301, 801), 12.5),
+    ((401, 1001), 12.5),
+    ((201, 201, 201), 12.5),
+)
+
+
+def serving_workload(idx: int, seed: int, small: bool = False) -> Workload:
+    """Request `idx` of a seeded serving mix: grid shape, shot count, r and the
+    model seed are drawn per request; sources at the surface, receivers on a
+    surface line (2D) or grid (3D).  `small` shrinks grids and records for
+    tests."""
+    rng = np.random.default_rng([seed, idx])
+    shape, h = SERVING_SHAPES[int(rng.integers(len(SERVING_SHAPES)))]
+    is3d = len(shape) == 3
+    shots = 1 if is3d else int(rng.choice([1, 2, 4, 8, 16, 32]))
+    r = int(rng.choice([8, 32, 64]))
+    f = float(rng.uniform(0.010, 0.015))
+    T = 2000.0 if h == 10.0 else 2500.0 if is3d else 3000.0
+    if small:
+        shape = tuple(max(24, s // 8) for s in shape)
+        shots = min(shots, 4)
+        T = 300.0
+        f = 0.02
+    vmin, vmax = 1.5, (4.0 if is3d else 4.5)
+    limit = 0.4529 if is3d else 0.5546
+    dt = float(np.floor(0.85 * limit * h / vmax * 100.0) / 100.0)
+    nt = int(round(T / dt)) + 1
+    X = (shape[-1] - 1) * h
+    if is3d:
+        Y = (shape[1] - 1) * h
+        src = [(0.5 * X, 0.5 * Y, 2 * h)]
+        step = 4 * h
+        rec = [(i * step, j * step, 2 * h) for j in range(int(Y // step) + 1) for i in range(int(X // step) + 1)]
+    else:
+        xs = np.linspace(0.1 * X, 0.9 * X, shots)
+        src = [(float(x), 0.0, 2 * h) for x in xs]
+        rec = [(i * 2 * h, 0.0, 2 * h) for i in range(int(X // (2 * h)) + 1)]
+    return Workload("serve_%d" % idx, tuple(shape), h, 8, dt, nt, f, vmin, vmax, nbl=20 if not small else 8,
+                    r=r, probe="rademacher", probe_seed=1000 + idx, model_seed=int(rng.integers(1 << 30)),
+                    smooth_sigma=6.0, src=src, rec=rec)

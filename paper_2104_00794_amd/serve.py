@@ -1,0 +1,179 @@
+"""Continuous-batching server for probed-gradient requests on one GPU.
+
+Requests (a grid, its acquisition, probes, the current model and the observed
+data, all resident on the device) arrive over time.  The server admits a
+request as soon as a slot is free and its workspace fits the HBM budget
+(``tpx_workspace_bytes`` gives the exact size), then advances every admitted
+job by a chunk of time steps at a time on its own HIP stream, so the work of
+several jobs overlaps on the device; requests that arrive while others run
+join at the next chunk boundary.  A job's results do not depend on its
+neighbours (separate workspaces, deterministic kernels).
+
+``run_sequential`` is the plain path: one ``tpx_gradient_probed`` call at a
+time in arrival order, on the same arrival trace.
+"""
+from __future__ import annotations
+
+import collections
+import time
+from dataclasses import dataclass
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import tpx
+
+
+@dataclass
+class Request:
+    rid: int
+    grid: tpx.Grid
+    geom: tpx.Geometry
+    probe: tpx.Probe
+    m: torch.Tensor
+    d_obs: torch.Tensor
+    arrival: float = 0.0          # seconds after the start of the run
+
+    @property
+    def updates(self) -> int:
+        """Grid-point updates of one gradient (forward + adjoint, padded grid)."""
+        npad = int(np.prod([s + 2 * self.grid.nbl for s in self.grid.shape]))
+        return self.geom.nshots * npad * 2 * (self.grid.nt - 1)
+
+    def workspace_bytes(self) -> int:
+        return tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, self.grid, self.geom, self.probe)
+
+
+@dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    g: Optional[torch.Tensor] = None
+    J: Optional[torch.Tensor] = None
+    status: str = "ok"
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class _Active:
+    def __init__(self, req: Request, job: tpx.Job, stream, need: int, admitted: float):
+        self.req, self.job, self.stream, self.need, self.admitted = req, job, stream, need, admitted
+        self.events = collections.deque()
+
+
+class Server:
+    def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 128, max_active: int = 16,
+                 nstreams: int = 8, inflight: int = 2, device=None):
+        self.budget = float(hbm_budget_bytes)
+        self.chunk = int(chunk_steps)
+        self.max_active = int(max_active)
+        self.inflight = int(inflight)
+        self.device = torch.device(device or "cuda")
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nstreams)]
+        self.peak_active = 0
+        self.peak_bytes = 0
+
+    def run(self, requests: List[Request]) -> Dict[int, Result]:
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        pend = collections.deque(reqs)
+        waiting = collections.deque()
+        active: List[_Active] = []
+        free_streams = list(self.streams)
+        used = 0
+        results: Dict[int, Result] = {}
+        t0 = time.perf_counter()
+        while pend or waiting or active:
+            now = time.perf_counter() - t0
+            while pend and pend[0].arrival <= now:
+                r = pend.popleft()
+                results[r.rid] = Result(r.rid, r.arrival)
+                waiting.append(r)
+            # admission at chunk boundaries, first come first served
+            while waiting and len(active) < self.max_active and free_streams:
+                req = waiting[0]
+                need = req.workspace_bytes() + 4 * int(np.prod(req.grid.shape)) + 8
+                if need > self.budget:
+                    waiting.popleft()
+                    results[req.rid].status = "rejected: workspace exceeds the HBM budget"
+                    results[req.rid].finished = now
+                    continue
+                if used + need > self.budget:
+                    break
+                waiting.popleft()
+                stream = free_streams.pop()
+                with torch.cuda.stream(stream):
+                    ws = torch.empty(req.workspace_bytes(), dtype=torch.uint8, device=self.device)
+                    job = tpx.Job(req.grid, req.geom, req.probe, req.m, req.d_obs, ws=ws, stream=stream)
+                active.append(_Active(req, job, stream, need, now))
+                results[req.rid].admitted = now
+                used += need
+                self.peak_active = max(self.peak_active, len(active))
+                self.peak_bytes = max(self.peak_bytes, used)
+            # advance every active job by one chunk, keeping a bounded queue per job
+            for st in list(active):
+                while st.events and st.events[0].query():
+                    st.events.popleft()
+                if st.job.finished:
+                    if not st.events:
+                        res = results[st.req.rid]
+                        res.finished = time.perf_counter() - t0
+                        res.g, res.J = st.job.g, st.job.J
+                        st.job.close()
+                        st.job.ws = None
+                        active.remove(st)
+                        free_streams.append(st.stream)
+                        used -= st.need
+                    continue
+                if len(st.events) < self.inflight:
+                    st.job.advance(self.chunk, stream=st.stream)
+                    ev = torch.cuda.Event()
+                    ev.record(st.stream)
+                    st.events.append(ev)
+            if not active and waiting and not free_streams:
+                raise RuntimeError("no stream available")
+            if not active and not waiting and pend:
+                time.sleep(max(0.0, min(pend[0].arrival - (time.perf_counter() - t0), 0.001)))
+        torch.cuda.synchronize(self.device)
+        return results
+
+
+def run_sequential(requests: List[Request], device=None) -> Dict[int, Result]:
+    """The plain path: one gradient call at a time, in arrival order."""
+    device = torch.device(device or "cuda")
+    reqs = sorted(requests, key=lambda r: r.arrival)
+    results: Dict[int, Result] = {}
+    stream = torch.cuda.current_stream(device)
+    t0 = time.perf_counter()
+    for req in reqs:
+        now = time.perf_counter() - t0
+        if req.arrival > now:
+            time.sleep(req.arrival - now)
+        res = Result(req.rid, req.arrival, admitted=time.perf_counter() - t0)
+        g, J = tpx.gradient_probed(req.grid, req.geom, req.probe, req.m, req.d_obs, stream=stream)
+        torch.cuda.synchronize(device)
+        res.finished = time.perf_counter() - t0
+        res.g, res.J = g, J
+        results[req.rid] = res
+    return results
+
+
+def summarize(results: Dict[int, Result], requests: List[Request]) -> dict:
+    ok = [r for r in results.values() if r.status == "ok"]
+    lat = np.array([r.latency for r in ok]) * 1e3
+    start = min(r.arrival for r in results.values())
+    end = max(r.finished for r in ok)
+    upd = sum(q.updates for q in requests if results[q.rid].status == "ok")
+    return {"requests": len(results), "completed": len(ok), "rejected": len(results) - len(ok),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mean_ms": round(float(lat.mean()), 2), "makespan_s": round(end - start, 3),
+            "gpts_per_s": round(upd / (end - start) / 1e9, 2)}
+
+
+def poisson_arrivals(n: int, rate_per_s: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n)) - 0.0

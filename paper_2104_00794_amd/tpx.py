@@ -87,11 +87,18 @@ def lib():
     L.tpx_backward_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp, vp, sz, vp]
     L.tpx_probe_matrix.argtypes = [P(_Probe), i32, i32, vp, vp]
     L.tpx_check_workspace.argtypes = [vp, vp]
+    L.tpx_job_create.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, vp, vp, vp, sz, vp,
+                                 P(ctypes.c_void_p)]
+    L.tpx_job_advance.argtypes = [vp, i32, vp, P(i32)]
+    L.tpx_job_progress.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
+    L.tpx_job_destroy.argtypes = [vp]
+    L.tpx_job_destroy.restype = None
     L.tpx_profile_enable.argtypes = [i32]
     L.tpx_profile_enable.restype = None
     L.tpx_profile_read.argtypes = [i32, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ("tpx_forward", "tpx_adjoint", "tpx_gradient_probed", "tpx_gradient_full", "tpx_forward_probed",
-                 "tpx_backward_probed", "tpx_probe_matrix", "tpx_check_workspace", "tpx_profile_read"):
+                 "tpx_backward_probed", "tpx_probe_matrix", "tpx_check_workspace", "tpx_profile_read",
+                 "tpx_job_create", "tpx_job_advance", "tpx_job_progress"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -346,6 +353,53 @@ def probe_matrix(probe: Probe, nt: int, shot: int, device=None, stream=None):
     pc = probe.c()
     _check(lib().tpx_probe_matrix(ctypes.byref(pc), int(nt), int(shot), Z.data_ptr(), _stream(stream)))
     return Z
+
+
+class Job:
+    """A probed-gradient job advanced a bounded number of time steps at a time.
+
+    The caller owns every buffer (model, data, outputs, workspace); they are
+    kept referenced here until the job is closed.
+    """
+
+    def __init__(self, grid: Grid, geom: Geometry, probe: Probe, m, d_obs, ws=None, stream=None, g=None, J=None):
+        torch = _torch()
+        _dev_f32(m, grid.shape, "m")
+        _dev_f32(d_obs, (geom.nshots, grid.nt, geom.nrec), "d_obs")
+        self.grid, self.geom, self.probe, self.m, self.d_obs = grid, geom, probe, m, d_obs
+        self.g = g if g is not None else torch.empty(tuple(grid.shape), dtype=torch.float32, device=m.device)
+        self.J = J if J is not None else torch.empty(1, dtype=torch.float64, device=m.device)
+        self.ws = _ws(ws, CALL_GRADIENT_PROBED, grid, geom, probe, m.device)
+        gc, ge, pc = grid.c(), geom.c(), probe.c()
+        h = ctypes.c_void_p()
+        _check(lib().tpx_job_create(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
+                                    d_obs.data_ptr(), self.g.data_ptr(), self.J.data_ptr(), None,
+                                    self.ws.data_ptr(), self.ws.numel(), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.finished = False
+
+    def advance(self, max_steps: int, stream=None) -> bool:
+        """Enqueue up to max_steps time steps; True once all work is enqueued."""
+        fin = ctypes.c_int32(0)
+        _check(lib().tpx_job_advance(self._h, int(max_steps), _stream(stream), ctypes.byref(fin)))
+        self.finished = bool(fin.value)
+        return self.finished
+
+    def progress(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tpx_job_progress(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
+
+    def close(self):
+        if self._h:
+            lib().tpx_job_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL = range(4)

@@ -1,0 +1,70 @@
+"""Serving: continuous batching of probed-gradient jobs on one GPU."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests.helpers import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    ensure_built()
+
+import torch  # noqa: E402
+
+from paper_2104_00794_amd import serve, tpx  # noqa: E402
+from paper_2104_00794_amd.inputs import serving_workload  # noqa: E402
+
+
+def make_request(i, seed=41, small=True, arrival=0.0):
+    wl = serving_workload(i, seed, small=small)
+    mt, m0 = wl.models()
+    dev = torch.device("cuda")
+    grid = tpx.Grid(wl.shape, h=wl.h, dt=wl.dt, nt=wl.nt, order=wl.order, nbl=wl.nbl, damp_vmax=wl.vmax)
+    geom = tpx.Geometry(wl.src_pos(), wl.rec_pos(), torch.tensor(wl.wavelet(), dtype=torch.float32, device=dev))
+    probe = tpx.Probe(r=wl.r, seed=wl.probe_seed)
+    d_obs = tpx.forward(grid, geom, torch.tensor(mt, dtype=torch.float32, device=dev))
+    m = torch.tensor(m0, dtype=torch.float32, device=dev)
+    return serve.Request(i, grid, geom, probe, m, d_obs, arrival)
+
+
+def test_job_in_chunks_equals_one_call():
+    req = make_request(3)
+    g, J = tpx.gradient_probed(req.grid, req.geom, req.probe, req.m, req.d_obs)
+    job = tpx.Job(req.grid, req.geom, req.probe, req.m, req.d_obs)
+    n = 0
+    while not job.advance(7):
+        n += 1
+    torch.cuda.synchronize()
+    assert n > 2
+    assert torch.equal(job.g, g) and torch.equal(job.J, J)
+    done, total = job.progress()
+    assert done == total == 2 * (req.grid.nt - 1)
+
+
+def test_results_identical_alone_and_in_the_mix():
+    reqs = [make_request(i, arrival=0.002 * i) for i in range(10)]
+    alone = serve.run_sequential(reqs)
+    srv = serve.Server(hbm_budget_bytes=50e9, chunk_steps=32, max_active=8, nstreams=6)
+    mixed = srv.run(reqs)
+    assert srv.peak_active > 1
+    for r in reqs:
+        a, b = alone[r.rid], mixed[r.rid]
+        assert b.status == "ok"
+        assert torch.equal(a.g, b.g), r.rid
+        assert torch.equal(a.J, b.J), r.rid
+    s = serve.summarize(mixed, reqs)
+    assert s["completed"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_admission_by_hbm_budget():
+    reqs = [make_request(i, arrival=0.0) for i in range(4)]
+    need = [r.workspace_bytes() for r in reqs]
+    budget = max(need) * 1.05 + 1e6     # room for one job at a time (the largest)
+    srv = serve.Server(hbm_budget_bytes=budget, chunk_steps=64, max_active=4, nstreams=4)
+    res = srv.run(reqs)
+    assert all(r.status == "ok" for r in res.values())
+    assert srv.peak_bytes <= budget
+    tiny = serve.Server(hbm_budget_bytes=min(need) / 2, chunk_steps=64)
+    res = tiny.run(reqs[:2])
+    assert all(r.status.startswith("rejected") for r in res.values())
