@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nt", type=int, default=0, help="time steps of the CPU-oracle sample (0 = full record)")
     ap.add_argument("--no-profile-pass", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving mix instead: continuous batching vs one-at-a-time on one Poisson trace")
+    ap.add_argument("--requests", type=int, default=60, help="requests in the serving trace")
+    ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget of the server")
     return ap.parse_args()
 
 
@@ -67,6 +71,9 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.serving:
+        return serving(args, dev)
 
     wl = workload(args.workload)
     if args.nt:
@@ -108,6 +115,12 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     lat = np.array([a.elapsed_time(b) for a, b in ev])
+    # host time to enqueue one call (the call returns once its work is queued)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    step()
+    host_enqueue_ms = (time.perf_counter() - th) * 1e3
+    torch.cuda.synchronize()
 
     S, npad, nphys, nt = wl.nshots, wl.n_pad, wl.n_phys, wl.nt
     updates = S * npad * 2 * (nt - 1)
@@ -144,7 +157,8 @@ def main():
     if not args.no_cpu_baseline:
         # about 10-30 s of oracle work: the full record of one 2D shot, or a
         # short window of the 3D record
-        cpu = cpu_baseline(wl, r, kind, args.cpu_nt or (wl.nt if wl.ndim == 2 else 24))
+        cpu = cpu_baseline(wl, r, kind, args.cpu_nt or (wl.nt if wl.ndim == 2 else 24),
+                           min(4, wl.nshots) if wl.ndim == 2 else 1)
 
     out = {
         "metric": "GPts/s fwd+adj with r-probe accumulation (%HBM roofline); gradient p50/p99 latency",
@@ -163,37 +177,83 @@ def main():
                    "space_order": wl.order, "shots": S, "nt": nt, "nbl": wl.nbl, "r": r, "probe": kind,
                    "block": args.block or "default", "keep_vbar": bool(args.keep_vbar),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
+        "host_enqueue_ms": round(host_enqueue_ms, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},
         "hbm_roofline_pct": round(100.0 * gpts * b_alg_path / HBM_PEAK_GBS, 2),
         "b_alg_bytes_per_point_step": round(b_alg_path, 3),
         "roofline": roofline,
         "kernels": kernels,
+        "kernel_timing": "HIP events on the launch stream around each run of consecutive launches of one "
+                         "kernel kind, in one profiled call after the timed region",
         "cpu_baseline": cpu,
         "J": float(J.item()),
     }
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, r, kind, nt_sample):
-    """FP64 oracle, one shot of the workload, first nt_sample time steps."""
+def serving(args, dev):
+    """Serving mix: p50/p99 latency and aggregate GPts/s, continuous batching vs
+    the plain one-at-a-time path on the same Poisson arrival trace."""
+    import torch
+    from paper_2104_00794_amd import serve, tpx
+    from paper_2104_00794_amd.inputs import serving_workload
+    reqs = []
+    for i in range(args.requests):
+        wl = serving_workload(i, 41)
+        mt, m0 = wl.models()
+        grid = tpx.Grid(wl.shape, h=wl.h, dt=wl.dt, nt=wl.nt, order=wl.order, nbl=wl.nbl, damp_vmax=wl.vmax)
+        geom = tpx.Geometry(wl.src_pos(), wl.rec_pos(), torch.tensor(wl.wavelet(), dtype=torch.float32, device=dev))
+        d_obs = tpx.forward(grid, geom, torch.tensor(mt, dtype=torch.float32, device=dev))
+        reqs.append(serve.Request(i, grid, geom, tpx.Probe(r=wl.r, seed=wl.probe_seed),
+                                  torch.tensor(m0, dtype=torch.float32, device=dev), d_obs))
+    torch.cuda.synchronize()
+    # service time of the plain path (also the warm-up), then the arrival rate
+    svc = serve.run_sequential(reqs)
+    mean_service = float(np.mean([r.finished - r.admitted for r in svc.values()]))
+    rate = 0.8 / mean_service
+    arr = serve.poisson_arrivals(len(reqs), rate, 41)
+    for q, a in zip(reqs, arr):
+        q.arrival = float(a)
+    seq = serve.run_sequential(reqs)
+    srv = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=128, max_active=16, nstreams=8)
+    bat = srv.run(reqs)
+    same = all(torch.equal(seq[q.rid].g, bat[q.rid].g) for q in reqs if bat[q.rid].status == "ok")
+    a, b = serve.summarize(seq, reqs), serve.summarize(bat, reqs)
+    out = {
+        "metric": "serving: gradient p50/p99 latency and aggregate GPts/s, continuous batching vs one-at-a-time",
+        "value": b["gpts_per_s"], "unit": "GPts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+        "data": "synthetic", "vs_baseline": None,
+        "config": {"workload": "serving mix: 2D 201x201..1001x401 (1-32 shots), 3D 201^3 (1 shot), "
+                               "r in {8,32,64}, order 8", "requests": len(reqs),
+                   "arrival": "Poisson, %.2f req/s = 0.8 x sequential service rate" % rate,
+                   "hbm_budget_gb": args.budget_gb, "chunk_steps": 128},
+        "batched": b, "sequential": a, "mean_service_ms": round(1e3 * mean_service, 2),
+        "peak_active_jobs": srv.peak_active, "peak_workspace_gb": round(srv.peak_bytes / 1e9, 2),
+        "results_identical": bool(same),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, r, kind, nt_sample, shots):
+    """FP64 oracle on the first `shots` shots of the workload, first nt_sample time steps."""
     import oracle
     oracle.build(force=False)
-    sample = wl.with_(nt=nt_sample, src=[wl.src[0]])
+    sample = wl.with_(nt=nt_sample, src=wl.src[:shots])
     mt, m0 = sample.models()
     og = oracle.Grid(sample.shape, h=sample.h, dt=sample.dt, nt=sample.nt, order=sample.order, nbl=sample.nbl,
                      damp_vmax=sample.vmax, damp_R=sample.damp_R)
-    dobs = np.zeros((1, sample.nt, len(sample.rec)))
+    dobs = np.zeros((sample.nshots, sample.nt, len(sample.rec)))
     t0 = time.perf_counter()
     oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind=kind, r=r,
                            seed=sample.probe_seed)
     dt = time.perf_counter() - t0
-    upd = sample.n_pad * 2 * (sample.nt - 1)
+    upd = sample.nshots * sample.n_pad * 2 * (sample.nt - 1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(upd / dt / 1e9, 5), "unit": "GPts/s", "cores": cores, "kind": "oracle",
             "seconds": round(dt, 2),
-            "sample": "1 of %d shots, first %d of %d time steps, r=%d %s, same grid; FP64 C oracle with OpenMP"
-                      % (wl.nshots, sample.nt, wl.nt, r, kind)}
+            "sample": "%d of %d shots, first %d of %d time steps, r=%d %s, same grid; FP64 C oracle with OpenMP"
+                      % (sample.nshots, wl.nshots, sample.nt, wl.nt, r, kind)}
 
 
 if __name__ == "__main__":

@@ -40,8 +40,9 @@
  * memory.  Each call validates its arguments on the host before any launch,
  * then enqueues its work on `stream` (a hipStream_t passed as void*, NULL =
  * the null stream) and returns; outputs are valid once the stream reaches the
- * end of the call.  A call uploads small geometry tables into the workspace
- * and waits for that upload (not for the heavy work) before returning.
+ * end of the call.  A call stages its geometry tables in pinned host memory
+ * owned by the library and uploads them into the workspace asynchronously, on
+ * the same stream; it never waits for the stream.
  * Two calls may run concurrently on different streams if their workspaces
  * and outputs do not overlap.  No C++ exception crosses this boundary.
  */
@@ -190,11 +191,11 @@ void tpx_job_destroy(tpx_job *job);
  * value, TPX_E_CFL if it held a velocity above damp_vmax. */
 tpx_status tpx_check_workspace(const void *ws, void *stream);
 
-/* Per-launch timing for measurement: while enabled, every launch of the
- * kernels below is bracketed by HIP events on its stream (this adds a little
- * host overhead).  Enabling clears earlier records; tpx_profile_read waits
- * for the recorded events and returns the summed duration and launch count
- * of one kernel kind. */
+/* Kernel timing for measurement: while enabled, each run of consecutive
+ * launches of one kernel kind on one stream is bracketed by a pair of HIP
+ * events on that stream (no events between the kernels of a run).  Enabling
+ * clears earlier records; tpx_profile_read waits for the recorded events and
+ * returns the summed duration and the launch count of one kernel kind. */
 enum {
     TPX_KERNEL_STEP = 0,      /* leapfrog step with fused injection/sampling */
     TPX_KERNEL_ACCUM_FWD = 1, /* forward probe contraction                   */

@@ -63,13 +63,16 @@ __device__ __forceinline__ float segment_value(const InjectTables &inj, const fl
 
 // ---------------------------------------------------------------------------
 // 2D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 32 (z) tile of
-// outputs; every thread produces eight outputs of one column.  All global
-// loads (u^k tile with its R-wide halo, u^{k-1}, beta) are issued before the
-// LDS barrier.  Only nodes of the padded box are read (outside it the field
-// is zero by definition), so ghost cells of the buffers need no clearing.  Blocks are numbered XCD-aware: the hardware hands block b to
-// XCD b mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8 gives every
-// XCD a contiguous run of tiles whose halos then hit in that XCD's L2.
-// Offsets within one shot field are 32-bit (a shot field is < 2^31 floats).
+// outputs.  u^k is staged with its R-wide halo in LDS; every thread then owns
+// eight consecutive rows of one column: it reads its column (8 + 2R values)
+// from LDS once and keeps it in registers (z neighbours), and reads only the
+// x neighbours per output from LDS.  All global loads are issued before the
+// barrier, from clamped in-box addresses with the result selected, so no load
+// sits behind a branch.  Blocks are numbered XCD-aware: the hardware hands
+// block b to XCD b mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8
+// gives every XCD a contiguous run of tiles whose halos then hit in that XCD's
+// L2.  Only nodes of the padded box are read (outside it the field is zero),
+// so ghost cells of the buffers need no clearing.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int xcd_logical_block(int nlogical) {
     const int per = (int)gridDim.x >> 3;
@@ -78,12 +81,14 @@ __device__ __forceinline__ int xcd_logical_block(int nlogical) {
     return lid < nlogical ? lid : -1;
 }
 
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
 template <int R>
 __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph, const StepArgs a) {
     constexpr int W = T2X + 2 * R;
     constexpr int H = T2Z + 2 * R;
-    constexpr int NL = (H + 3) / 4;
-    constexpr int NQ = T2Z / 4;
+    constexpr int NL = (H + 3) / 4;   // staged rows per thread
+    constexpr int NQ = T2Z / 4;       // outputs per thread (consecutive rows)
     __shared__ float tile[H][W];
 
     const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2];
@@ -100,24 +105,31 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
     const float *beta = a.beta + XO;
     float *next = a.next + shot * L.shot_floats + XO;
 
+    const int gx = x0 - R + lx, gx2 = gx + 64;
+    const bool xin = gx >= 0 && gx < P0, xin2 = lx < 2 * R && gx2 < P0;
+    const int gxc = clampi(gx, 0, P0 - 1), gxc2 = clampi(gx2, 0, P0 - 1);
     float t[NL], t2[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         const int row = ly + 4 * i, gz = z0 - R + row;
-        const bool rok = row < H && gz >= 0 && gz < P2;
-        const int gx = x0 - R + lx, gx2 = gx + 64;
-        t[i] = (rok && gx >= 0 && gx < P0) ? cur[(gz + R) * G0 + gx] : 0.0f;
-        t2[i] = (rok && lx < 2 * R && gx2 < P0) ? cur[(gz + R) * G0 + gx2] : 0.0f;
+        const bool zin = row < H && gz >= 0 && gz < P2;
+        const int ro = (clampi(gz, 0, P2 - 1) + R) * G0;
+        const float v = cur[ro + gxc];
+        t[i] = (zin && xin) ? v : 0.0f;
+        t2[i] = (zin && xin2) ? cur[ro + gxc2] : 0.0f;
     }
+    const int x = x0 + lx, zb = z0 + ly * NQ;
+    const bool xo = x < P0;
+    const int xc = xo ? x : P0 - 1;
     float p[NQ], b[NQ];
-    const int x = x0 + lx;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int z = z0 + ly + 4 * q;
-        const bool ok = z < P2 && x < P0;
-        const int off = (z + R) * G0 + x;
-        p[q] = ok ? prev[off] : 0.0f;
-        b[q] = ok ? beta[off] : 0.0f;
+        const int z = zb + q;
+        const int off = (clampi(z, 0, P2 - 1) + R) * G0 + xc;
+        const float pv = prev[off], bv = beta[off];
+        const bool ok = xo && z < P2;
+        p[q] = ok ? pv : 0.0f;
+        b[q] = ok ? bv : 0.0f;
     }
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
@@ -141,30 +153,32 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
                 const int loc = a.inj.seg_local[sg];          // lz * 64 + lx of the target node
                 const float v = segment_value(a.inj, amp, a.amp.scale, sg);
                 const int lz = loc >> 6;
-                if ((loc & 63) == lx && (lz & 3) == ly) {
+                if ((loc & 63) == lx && lz / NQ == ly) {
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
-                        if ((lz >> 2) == q) src[q] += v;
+                        if (lz - ly * NQ == q) src[q] += v;
                 }
             }
         }
     }
     __syncthreads();
 
+    float col[NQ + 2 * R];
+#pragma unroll
+    for (int i = 0; i < NQ + 2 * R; ++i) col[i] = tile[ly * NQ + i][lx + R];
     const float hx = layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int lz = ly + 4 * q;
-        const int z = z0 + lz;
-        if (z >= P2 || x >= P0) continue;
-        const float c = tile[lz + R][lx + R];
+        const int z = zb + q, lr = ly * NQ + q + R;
+        const float c = col[q + R];
         float lap = 2.0f * ph.c[0] * c;
 #pragma unroll
         for (int k = 1; k <= R; ++k)
-            lap += ph.c[k] * ((tile[lz + R][lx + R - k] + tile[lz + R][lx + R + k]) +
-                              (tile[lz + R - k][lx + R] + tile[lz + R + k][lx + R]));
-        const float hd = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
-        next[(z + R) * G0 + x] = leapfrog(c, p[q], b[q], lap, src[q], hd);
+            lap += ph.c[k] * ((tile[lr][lx + R - k] + tile[lr][lx + R + k]) + (col[q + R - k] + col[q + R + k]));
+        if (z < P2 && xo) {
+            const float hd = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
+            next[(z + R) * G0 + x] = leapfrog(c, p[q], b[q], lap, src[q], hd);
+        }
     }
 
     if (a.do_sample) {
@@ -480,116 +494,115 @@ __device__ __forceinline__ PointIndex point_index(const Layout &L) {
 
 constexpr int kAccUnroll = 8;   // buffered steps whose loads are issued together
 
+// Buffered slots are read exactly once by a contraction.
+__device__ __forceinline__ float ring_load(const float *p) {
+#ifdef TPX_RING_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+// Forward contraction of exactly RC probes j0..j0+RC-1 (no per-probe
+// predicates: the launcher splits r into power-of-two chunks).
 template <int RC>
 __global__ __launch_bounds__(256) void k_accum_fwd(const Layout L, const float *__restrict__ ring, int nslots,
                                                    int s_lo, int s_hi, const float *__restrict__ Z, int nt, int r,
-                                                   float *__restrict__ ubar) {
+                                                   int j0, float *__restrict__ ubar) {
     const PointIndex pi = point_index(L);
     if (!pi.ok) return;
     const int shot = blockIdx.y;
     const float *base = ring + shot * L.shot_floats + pi.off;
-    for (int j0 = 0; j0 < r; j0 += RC) {
-        const int rc = (r - j0) < RC ? (r - j0) : RC;
-        float acc[RC];
+    const float *Zs = Z + (int64_t)shot * nt * r + j0;
+    float acc[RC];
 #pragma unroll
-        for (int j = 0; j < RC; ++j) acc[j] = 0.0f;
-        int s = s_lo;
-        for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
-            float v[kAccUnroll];
+    for (int j = 0; j < RC; ++j) acc[j] = 0.0f;
+    int s = s_lo;
+    for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
+        float v[kAccUnroll];
 #pragma unroll
-            for (int u = 0; u < kAccUnroll; ++u) v[u] = base[(int64_t)((s + u) % nslots) * L.slot_floats];
+        for (int u = 0; u < kAccUnroll; ++u) v[u] = ring_load(&base[(int64_t)((s + u) % nslots) * L.slot_floats]);
 #pragma unroll
-            for (int u = 0; u < kAccUnroll; ++u) {
-                const float *zr = Z + ((int64_t)shot * nt + s + u) * r + j0;
+        for (int u = 0; u < kAccUnroll; ++u) {
+            const float *zr = Zs + (int64_t)(s + u) * r;
 #pragma unroll
-                for (int j = 0; j < RC; ++j)
-                    if (j < rc) acc[j] = fmaf(zr[j], v[u], acc[j]);
-            }
+            for (int j = 0; j < RC; ++j) acc[j] = fmaf(zr[j], v[u], acc[j]);
         }
-        for (; s <= s_hi; ++s) {
-            const float v = base[(int64_t)(s % nslots) * L.slot_floats];
-            const float *zr = Z + ((int64_t)shot * nt + s) * r + j0;
-#pragma unroll
-            for (int j = 0; j < RC; ++j)
-                if (j < rc) acc[j] = fmaf(zr[j], v, acc[j]);
-        }
-        float *ub = ubar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
-#pragma unroll
-        for (int j = 0; j < RC; ++j)
-            if (j < rc) ub[(int64_t)j * L.nphys] += acc[j];
     }
+    for (; s <= s_hi; ++s) {
+        const float v = ring_load(&base[(int64_t)(s % nslots) * L.slot_floats]);
+        const float *zr = Zs + (int64_t)s * r;
+#pragma unroll
+        for (int j = 0; j < RC; ++j) acc[j] = fmaf(zr[j], v, acc[j]);
+    }
+    float *ub = ubar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
+#pragma unroll
+    for (int j = 0; j < RC; ++j) ub[(int64_t)j * L.nphys] += acc[j];
 }
 
 // One buffered step of the adjoint contraction: w = lam^{s-1} - 2 lam^s + lam^{s+1}.
 template <int RC, int FOLD>
-__device__ __forceinline__ void adj_step(float &lm, float &l0, float lp, const float *zr, int rc, const float *u,
-                                         float *acc, float &fsum) {
+__device__ __forceinline__ void adj_step(float &lm, float &l0, float lp, const float *zr, const float *u, float *acc,
+                                         float &fsum) {
     const float w = (lm - 2.0f * l0) + lp;
     if (FOLD) {
         float t = 0.0f;
 #pragma unroll
-        for (int j = 0; j < RC; ++j)
-            if (j < rc) t = fmaf(zr[j], u[j], t);
+        for (int j = 0; j < RC; ++j) t = fmaf(zr[j], u[j], t);
         fsum = fmaf(w, t, fsum);
     } else {
 #pragma unroll
-        for (int j = 0; j < RC; ++j)
-            if (j < rc) acc[j] = fmaf(zr[j], w, acc[j]);
+        for (int j = 0; j < RC; ++j) acc[j] = fmaf(zr[j], w, acc[j]);
     }
     lm = l0;
     l0 = lp;
 }
 
+// Adjoint contraction of exactly RC probes j0..j0+RC-1: either
+// vbar_j += sum_s Z[s,j] w^s, or (FOLD) gpart -= c sum_s w^s sum_j Z[s,j] ubar_j.
 template <int RC, int FOLD>
 __global__ __launch_bounds__(256) void k_accum_adj(const Layout L, const float *__restrict__ ring, int nslots,
                                                    int s_lo, int s_hi, const float *__restrict__ Z, int nt, int r,
-                                                   const float *__restrict__ ubar, float c,
+                                                   int j0, const float *__restrict__ ubar, float c,
                                                    float *__restrict__ vbar, float *__restrict__ gpart) {
     const PointIndex pi = point_index(L);
     if (!pi.ok) return;
     const int shot = blockIdx.y;
     const float *base = ring + shot * L.shot_floats + pi.off;
-    float gacc = 0.0f;
-    for (int j0 = 0; j0 < r; j0 += RC) {
-        const int rc = (r - j0) < RC ? (r - j0) : RC;
-        float u[RC];
-        float acc[RC];
+    const float *Zs = Z + (int64_t)shot * nt * r + j0;
+    float u[RC];
+    float acc[RC];
 #pragma unroll
-        for (int j = 0; j < RC; ++j) {
-            acc[j] = 0.0f;
-            u[j] = 0.0f;
-        }
-        if (FOLD) {
-            const float *ub = ubar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
-#pragma unroll
-            for (int j = 0; j < RC; ++j)
-                if (j < rc) u[j] = ub[(int64_t)j * L.nphys];
-        }
-        float lm = base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats];
-        float l0 = base[(int64_t)(s_lo % nslots) * L.slot_floats];
-        float fsum = 0.0f;
-        int s = s_lo;
-        for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
-            float lp[kAccUnroll];
-#pragma unroll
-            for (int q = 0; q < kAccUnroll; ++q) lp[q] = base[(int64_t)((s + q + 1) % nslots) * L.slot_floats];
-#pragma unroll
-            for (int q = 0; q < kAccUnroll; ++q)
-                adj_step<RC, FOLD>(lm, l0, lp[q], Z + ((int64_t)shot * nt + s + q) * r + j0, rc, u, acc, fsum);
-        }
-        for (; s <= s_hi; ++s)
-            adj_step<RC, FOLD>(lm, l0, base[(int64_t)((s + 1) % nslots) * L.slot_floats],
-                               Z + ((int64_t)shot * nt + s) * r + j0, rc, u, acc, fsum);
-        if (FOLD) {
-            gacc += fsum;
-        } else {
-            float *vb = vbar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
-#pragma unroll
-            for (int j = 0; j < RC; ++j)
-                if (j < rc) vb[(int64_t)j * L.nphys] += acc[j];
-        }
+    for (int j = 0; j < RC; ++j) {
+        acc[j] = 0.0f;
+        u[j] = 0.0f;
     }
-    if (FOLD) gpart[(int64_t)shot * L.nphys + pi.p] -= c * gacc;
+    if (FOLD) {
+        const float *ub = ubar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
+#pragma unroll
+        for (int j = 0; j < RC; ++j) u[j] = ub[(int64_t)j * L.nphys];
+    }
+    float lm = ring_load(&base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats]);
+    float l0 = ring_load(&base[(int64_t)(s_lo % nslots) * L.slot_floats]);
+    float fsum = 0.0f;
+    int s = s_lo;
+    for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
+        float lp[kAccUnroll];
+#pragma unroll
+        for (int q = 0; q < kAccUnroll; ++q) lp[q] = ring_load(&base[(int64_t)((s + q + 1) % nslots) * L.slot_floats]);
+#pragma unroll
+        for (int q = 0; q < kAccUnroll; ++q) adj_step<RC, FOLD>(lm, l0, lp[q], Zs + (int64_t)(s + q) * r, u, acc, fsum);
+    }
+    for (; s <= s_hi; ++s)
+        adj_step<RC, FOLD>(lm, l0, ring_load(&base[(int64_t)((s + 1) % nslots) * L.slot_floats]),
+                           Zs + (int64_t)s * r, u, acc, fsum);
+    if (FOLD) {
+        gpart[(int64_t)shot * L.nphys + pi.p] -= c * fsum;
+    } else {
+        float *vb = vbar + ((int64_t)shot * r + j0) * L.nphys + pi.p;
+#pragma unroll
+        for (int j = 0; j < RC; ++j) vb[(int64_t)j * L.nphys] += acc[j];
+    }
 }
 
 __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float *__restrict__ hist,
@@ -600,16 +613,16 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
     const int shot = blockIdx.y;
     const float *hb = hist + shot * L.shot_floats + pi.off;
     const float *base = ring + shot * L.shot_floats + pi.off;
-    float lm = base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats];
-    float l0 = base[(int64_t)(s_lo % nslots) * L.slot_floats];
+    float lm = ring_load(&base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats]);
+    float l0 = ring_load(&base[(int64_t)(s_lo % nslots) * L.slot_floats]);
     float acc = 0.0f;
     int s = s_lo;
     for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
         float lp[kAccUnroll], uh[kAccUnroll];
 #pragma unroll
         for (int q = 0; q < kAccUnroll; ++q) {
-            lp[q] = base[(int64_t)((s + q + 1) % nslots) * L.slot_floats];
-            uh[q] = hb[(int64_t)(s + q) * L.slot_floats];
+            lp[q] = ring_load(&base[(int64_t)((s + q + 1) % nslots) * L.slot_floats]);
+            uh[q] = ring_load(&hb[(int64_t)(s + q) * L.slot_floats]);
         }
 #pragma unroll
         for (int q = 0; q < kAccUnroll; ++q) {
@@ -620,9 +633,9 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
         }
     }
     for (; s <= s_hi; ++s) {
-        const float lp = base[(int64_t)((s + 1) % nslots) * L.slot_floats];
+        const float lp = ring_load(&base[(int64_t)((s + 1) % nslots) * L.slot_floats]);
         const float w = (lm - 2.0f * l0) + lp;
-        acc = fmaf(hb[(int64_t)s * L.slot_floats], w, acc);
+        acc = fmaf(ring_load(&hb[(int64_t)s * L.slot_floats]), w, acc);
         lm = l0;
         l0 = lp;
     }
@@ -633,25 +646,54 @@ static dim3 point_grid(const Layout &L) {
     return dim3((unsigned)((L.nphys + 255) / 256), (unsigned)L.S);
 }
 
+// largest power of two <= min(64, n)
+static int chunk_of(int n) {
+    int c = 64;
+    while (c > n) c >>= 1;
+    return c;
+}
+
 hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,
                             int nt, int r, float *ubar, hipStream_t stream) {
     if (s_hi < s_lo) return hipSuccess;
     const dim3 g = point_grid(L);
-    if (r <= 8) hipLaunchKernelGGL(k_accum_fwd<8>, g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar);
-    else if (r <= 16) hipLaunchKernelGGL(k_accum_fwd<16>, g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar);
-    else if (r <= 32) hipLaunchKernelGGL(k_accum_fwd<32>, g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar);
-    else hipLaunchKernelGGL(k_accum_fwd<64>, g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar);
+    for (int j0 = 0; j0 < r;) {
+        const int rc = chunk_of(r - j0);
+#define TPX_FWD(RC) hipLaunchKernelGGL(k_accum_fwd<RC>, g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar)
+        switch (rc) {
+        case 64: TPX_FWD(64); break;
+        case 32: TPX_FWD(32); break;
+        case 16: TPX_FWD(16); break;
+        case 8: TPX_FWD(8); break;
+        case 4: TPX_FWD(4); break;
+        case 2: TPX_FWD(2); break;
+        default: TPX_FWD(1); break;
+        }
+#undef TPX_FWD
+        j0 += rc;
+    }
     return hipGetLastError();
 }
 
 template <int FOLD>
-static void launch_adj_rc(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots, int s_lo,
-                          int s_hi, const float *Z, int nt, int r, const float *ubar, float c, float *vbar,
-                          float *gpart) {
-    if (r <= 8) hipLaunchKernelGGL((k_accum_adj<8, FOLD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
-    else if (r <= 16) hipLaunchKernelGGL((k_accum_adj<16, FOLD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
-    else if (r <= 32) hipLaunchKernelGGL((k_accum_adj<32, FOLD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
-    else hipLaunchKernelGGL((k_accum_adj<64, FOLD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+static void launch_adj_chunks(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots, int s_lo,
+                              int s_hi, const float *Z, int nt, int r, const float *ubar, float c, float *vbar,
+                              float *gpart) {
+    for (int j0 = 0; j0 < r;) {
+        const int rc = chunk_of(r - j0);
+#define TPX_ADJ(RC) hipLaunchKernelGGL((k_accum_adj<RC, FOLD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar, c, vbar, gpart)
+        switch (rc) {
+        case 64: TPX_ADJ(64); break;
+        case 32: TPX_ADJ(32); break;
+        case 16: TPX_ADJ(16); break;
+        case 8: TPX_ADJ(8); break;
+        case 4: TPX_ADJ(4); break;
+        case 2: TPX_ADJ(2); break;
+        default: TPX_ADJ(1); break;
+        }
+#undef TPX_ADJ
+        j0 += rc;
+    }
 }
 
 hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,
@@ -659,8 +701,8 @@ hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int 
                             hipStream_t stream) {
     if (s_hi < s_lo) return hipSuccess;
     const dim3 g = point_grid(L);
-    if (fold) launch_adj_rc<1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
-    else launch_adj_rc<0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    if (fold) launch_adj_chunks<1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    else launch_adj_chunks<0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
     return hipGetLastError();
 }
 

@@ -41,15 +41,23 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // ---------------------------------------------------------------------------
 struct ProfRec {
     int kind;
+    int64_t launches;
     hipEvent_t a, b;
 };
 
+// Consecutive launches of one kernel kind on one stream form a run that is
+// bracketed by a single pair of events, so the timing adds no event packets
+// between the kernels of a run.
 struct Profiler {
     std::mutex mu;
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<ProfRec> recs;
+    int run_kind = -1;
+    int64_t run_launches = 0;
+    hipStream_t run_stream = nullptr;
+    hipEvent_t run_start = nullptr;
 };
 
 Profiler &profiler() {
@@ -66,19 +74,35 @@ hipEvent_t take_event(Profiler &p) {
     return p.pool[p.used++];
 }
 
+void close_run(Profiler &p) {
+    if (p.run_kind < 0) return;
+    hipEvent_t b = take_event(p);
+    if (b && hipEventRecord(b, p.run_stream) == hipSuccess)
+        p.recs.push_back({p.run_kind, p.run_launches, p.run_start, b});
+    p.run_kind = -1;
+    p.run_launches = 0;
+}
+
+enum { KIND_OTHER = 99 };
+
 template <class F>
 hipError_t prof(int kind, hipStream_t s, F &&launch) {
     Profiler &p = profiler();
     if (!p.on) return launch();
     std::lock_guard<std::mutex> lk(p.mu);
-    hipEvent_t a = take_event(p), b = take_event(p);
-    if (!a || !b) return launch();
-    hipError_t e = hipEventRecord(a, s);
-    if (e != hipSuccess) return e;
-    e = launch();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, s);
-    if (e == hipSuccess) p.recs.push_back({kind, a, b});
+    if (kind != p.run_kind || s != p.run_stream) {
+        close_run(p);
+        hipEvent_t a = take_event(p);
+        if (!a) return launch();
+        hipError_t e = hipEventRecord(a, s);
+        if (e != hipSuccess) return e;
+        p.run_kind = kind;
+        p.run_stream = s;
+        p.run_start = a;
+        p.run_launches = 0;
+    }
+    const hipError_t e = launch();
+    if (e == hipSuccess) ++p.run_launches;
     return e;
 }
 
@@ -469,6 +493,57 @@ SampleTables dev_sample(unsigned char *base, const HostSample &h) {
     return t;
 }
 
+// Host-to-device upload of the geometry tables without waiting for the
+// stream: the bytes are staged in pinned host memory owned by the library and
+// a staging buffer is reused only after the event recorded behind its copy has
+// completed.
+struct Staging {
+    void *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+
+std::mutex g_stage_mu;
+std::vector<Staging> g_stage;
+
+hipError_t upload_async(void *dst, const void *src, size_t n, hipStream_t stream) {
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    Staging *use = nullptr;
+    for (Staging &st : g_stage) {
+        if (hipEventQuery(st.done) != hipSuccess) continue;   // copy still pending
+        if (st.cap >= n) {
+            use = &st;
+            break;
+        }
+        if (!use) use = &st;   // idle but small: grow it
+    }
+    if (!use) {
+        g_stage.emplace_back();
+        use = &g_stage.back();
+        hipError_t e = hipEventCreateWithFlags(&use->done, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    if (use->cap < n) {
+        if (use->host) {
+            hipError_t e = hipHostFree(use->host);
+            if (e != hipSuccess) return e;
+            use->host = nullptr;
+            use->cap = 0;
+        }
+        hipError_t e = hipHostMalloc(&use->host, n, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        use->cap = n;
+    }
+    memcpy(use->host, src, n);
+    hipError_t e = hipMemcpyAsync(dst, use->host, n, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(use->done, stream);
+}
+
+hipError_t fill_zero_p(void *ptr, size_t bytes, hipStream_t stream) {
+    return prof(KIND_OTHER, stream, [&] { return launch_fill_zero(ptr, bytes, stream); });
+}
+
 tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe *pr, Mode mode, const float *m,
                  void *ws, size_t ws_bytes, void *stream) {
     tpx_status st = make_problem(g, geo, &C.P);
@@ -495,19 +570,18 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     C.ws = (unsigned char *)ws;
     C.stream = (hipStream_t)stream;
     unsigned char *tb = C.ws + C.plan.tables;
-    if (!T.blob.bytes.empty()) {
-        TPX_HIP(hipMemcpyAsync(tb, T.blob.bytes.data(), T.blob.bytes.size(), hipMemcpyHostToDevice, C.stream));
-        TPX_HIP(hipStreamSynchronize(C.stream));  // the host blob is released on return
-    }
+    if (!T.blob.bytes.empty()) TPX_HIP(upload_async(tb, T.blob.bytes.data(), T.blob.bytes.size(), C.stream));
     C.src_inj = dev_inject(tb, T.src_inj);
     C.rec_inj = dev_inject(tb, T.rec_inj);
     C.rec_smp = dev_sample(tb, T.rec_smp);
     C.src_smp = dev_sample(tb, T.src_smp);
     C.beta = (float *)(C.ws + C.plan.beta);
     C.ring = (float *)(C.ws + C.plan.ring);
-    TPX_HIP(launch_fill_zero(C.ws + C.plan.flags, kAlign, C.stream));
+    TPX_HIP(fill_zero_p(C.ws + C.plan.flags, kAlign, C.stream));
     const float m_min = (float)(1.0 / (g->damp_vmax * g->damp_vmax) * (1.0 - 1e-5));
-    TPX_HIP(launch_model_prep(C.P.L, m, C.P.dt, m_min, C.beta, (int32_t *)(C.ws + C.plan.flags), C.stream));
+    TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
+        return launch_model_prep(C.P.L, m, C.P.dt, m_min, C.beta, (int32_t *)(C.ws + C.plan.flags), C.stream);
+    }));
     return TPX_OK;
 }
 
@@ -547,8 +621,8 @@ tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *
     f.finished = false;
     // u^{-1} = u^0 = 0: the first step reads slot 0 as both levels.  Other
     // slots are written before they are read, and ghost cells are never read.
-    TPX_HIP(launch_fill_zero(slot_ptr(f.buf, L, f.ns, 0), (size_t)L.slot_floats * 4, C.stream));
-    if (ubar) TPX_HIP(launch_fill_zero(ubar, align_up((size_t)L.S * r * L.nphys * 4), C.stream));
+    TPX_HIP(fill_zero_p(slot_ptr(f.buf, L, f.ns, 0), (size_t)L.slot_floats * 4, C.stream));
+    if (ubar) TPX_HIP(fill_zero_p(ubar, align_up((size_t)L.S * r * L.nphys * 4), C.stream));
     StepArgs &a = f.a;
     memset(&a, 0, sizeof a);
     a.beta = C.beta;
@@ -589,7 +663,7 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
         }
     }
     if (f.k > nt - 2 && !f.finished) {
-        if (a.do_sample) TPX_HIP(launch_sample_only(L, slot_ptr(f.buf, L, f.ns, nt - 1), nt - 1, f.smp, C.stream));
+        if (a.do_sample) TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(f.buf, L, f.ns, nt - 1), nt - 1, f.smp, C.stream); }));
         f.finished = true;
     }
     if (used) *used = n;
@@ -636,10 +710,10 @@ tpx_status adj_begin(Ctx &C, AdjLoop &b, const float *amp, const AdjOut &o) {
     b.s_hi = nt - 1;
     b.finished = false;
     // lambda^{nt} = lambda^{nt-1} = 0; every other slot is written before it is read
-    TPX_HIP(launch_fill_zero(slot_ptr(C.ring, L, ns, nt), (size_t)L.slot_floats * 4, C.stream));
-    TPX_HIP(launch_fill_zero(slot_ptr(C.ring, L, ns, nt - 1), (size_t)L.slot_floats * 4, C.stream));
-    if (o.gpart) TPX_HIP(launch_fill_zero(o.gpart, align_up((size_t)L.S * L.nphys * 4), C.stream));
-    if (o.vbar) TPX_HIP(launch_fill_zero(o.vbar, align_up((size_t)L.S * o.r * L.nphys * 4), C.stream));
+    TPX_HIP(fill_zero_p(slot_ptr(C.ring, L, ns, nt), (size_t)L.slot_floats * 4, C.stream));
+    TPX_HIP(fill_zero_p(slot_ptr(C.ring, L, ns, nt - 1), (size_t)L.slot_floats * 4, C.stream));
+    if (o.gpart) TPX_HIP(fill_zero_p(o.gpart, align_up((size_t)L.S * L.nphys * 4), C.stream));
+    if (o.vbar) TPX_HIP(fill_zero_p(o.vbar, align_up((size_t)L.S * o.r * L.nphys * 4), C.stream));
     StepArgs &a = b.a;
     memset(&a, 0, sizeof a);
     a.beta = C.beta;
@@ -689,7 +763,7 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
         }
     }
     if (b.k < 1 && !b.finished) {
-        if (o.q_adj) TPX_HIP(launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, b.smp, C.stream));
+        if (o.q_adj) TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, b.smp, C.stream); }));
         b.finished = true;
     }
     if (used) *used = n;
@@ -707,7 +781,7 @@ const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, tpx_status *st) {
     *st = TPX_OK;
     if (pr->kind == TPX_PROBE_EXPLICIT) return pr->Z;
     float *Z = (float *)(C.ws + C.plan.Z);
-    hipError_t e = launch_probe_gen(pr->kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream);
+    hipError_t e = prof(KIND_OTHER, C.stream, [&] { return launch_probe_gen(pr->kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream); });
     if (e != hipSuccess) *st = fail(TPX_E_DEVICE, std::string("probe generation: ") + hipGetErrorString(e));
     return Z;
 }
@@ -788,8 +862,10 @@ tpx_status job_advance(GradJob &J, int64_t max_steps) {
         if (J.f.finished) {
             const Layout &L = J.C.P.L;
             const int64_t ntr = (int64_t)L.S * J.C.P.nt * J.C.P.nrec;
-            TPX_HIP(launch_residual(J.d, J.d_obs, J.res, ntr, (double *)(J.C.ws + J.C.plan.parts),
-                                    residual_parts(ntr), J.J, J.C.stream));
+            TPX_HIP(prof(KIND_OTHER, J.C.stream, [&] {
+                return launch_residual(J.d, J.d_obs, J.res, ntr, (double *)(J.C.ws + J.C.plan.parts),
+                                       residual_parts(ntr), J.J, J.C.stream);
+            }));
             AdjOut o;
             o.Z = J.Z;
             o.r = J.probe.r;
@@ -808,8 +884,10 @@ tpx_status job_advance(GradJob &J, int64_t max_steps) {
         J.done_steps += used;
         if (J.b.finished) {
             const Layout &L = J.C.P.L;
-            if (J.probe.keep_vbar) TPX_HIP(launch_image_probed(L, J.probe.r, J.b.o.c, J.ubar, J.b.o.vbar, J.g, J.C.stream));
-            else TPX_HIP(launch_image_sum(L, J.b.o.gpart, J.g, J.C.stream));
+            TPX_HIP(prof(KIND_OTHER, J.C.stream, [&] {
+                return J.probe.keep_vbar ? launch_image_probed(L, J.probe.r, J.b.o.c, J.ubar, J.b.o.vbar, J.g, J.C.stream)
+                                         : launch_image_sum(L, J.b.o.gpart, J.g, J.C.stream);
+            }));
             J.phase = 2;
         }
     }
@@ -953,14 +1031,16 @@ tpx_status tpx_gradient_full(const tpx_grid *grid, const tpx_geom *geom, const f
         st = run_forward(C, geom->wavelet, d, hist, nullptr, 0, nullptr);
         if (st != TPX_OK) return st;
         const int64_t ntr = (int64_t)L.S * C.P.nt * C.P.nrec;
-        TPX_HIP(launch_residual(d, d_obs, res, ntr, (double *)(C.ws + C.plan.parts), residual_parts(ntr), J,
-                                C.stream));
+        TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
+            return launch_residual(d, d_obs, res, ntr, (double *)(C.ws + C.plan.parts), residual_parts(ntr), J,
+                                   C.stream);
+        }));
         AdjOut o;
         o.hist = hist;
         o.gpart = (float *)(C.ws + C.plan.gpart);
         st = run_adjoint(C, res, o);
         if (st != TPX_OK) return st;
-        TPX_HIP(launch_image_sum(L, o.gpart, g, C.stream));
+        TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_image_sum(L, o.gpart, g, C.stream); }));
         return TPX_OK;
     });
 }
@@ -1003,8 +1083,10 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
         o.gpart = probe->keep_vbar ? nullptr : (float *)(C.ws + C.plan.gpart);
         st = run_adjoint(C, grad_d, o);
         if (st != TPX_OK) return st;
-        if (probe->keep_vbar) TPX_HIP(launch_image_probed(L, probe->r, o.c, o.ubar, o.vbar, g, C.stream));
-        else TPX_HIP(launch_image_sum(L, o.gpart, g, C.stream));
+        TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
+            return probe->keep_vbar ? launch_image_probed(L, probe->r, o.c, o.ubar, o.vbar, g, C.stream)
+                                    : launch_image_sum(L, o.gpart, g, C.stream);
+        }));
         return TPX_OK;
     });
 }
@@ -1012,6 +1094,7 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
 void tpx_profile_enable(int32_t on) {
     Profiler &p = profiler();
     std::lock_guard<std::mutex> lk(p.mu);
+    close_run(p);
     if (on) {
         p.recs.clear();
         p.used = 0;
@@ -1024,6 +1107,7 @@ tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches) {
         if (!total_ms || !launches) return fail(TPX_E_INVAL, "total_ms and launches must not be NULL");
         Profiler &p = profiler();
         std::lock_guard<std::mutex> lk(p.mu);
+        close_run(p);
         double tot = 0.0;
         int64_t n = 0;
         for (const ProfRec &r : p.recs) {
@@ -1032,7 +1116,7 @@ tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches) {
             float ms = 0.0f;
             TPX_HIP(hipEventElapsedTime(&ms, r.a, r.b));
             tot += ms;
-            ++n;
+            n += r.launches;
         }
         *total_ms = tot;
         *launches = n;

@@ -16,7 +16,8 @@ from typing import Optional, Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libtpx.so")
+# TPX_LIBRARY may point at another build of the same library (e.g. a tuning build)
+LIB_PATH = os.environ.get("TPX_LIBRARY") or os.path.join(_HERE, "_build", "libtpx.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "tpx.h")
 
 OK, E_INVAL, E_CFL, E_GEOM, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE = range(8)
