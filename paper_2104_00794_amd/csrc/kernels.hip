@@ -50,10 +50,7 @@ __device__ __forceinline__ void sample_points(const Layout &L, const float *fiel
     }
 }
 
-// Source term of one injection segment (one target node): its entries
-// summed in their stored order.  Every argument is uniform across the block,
-// so the whole block evaluates it redundantly with scalar loads and the single
-// thread that owns the node adds it to its output.
+// Source term of one target node: its entries summed in their stored order.
 __device__ __forceinline__ float segment_value(const InjectTables &inj, const float *a, float scale, int sg) {
     float acc = 0.0f;
     const int e1 = inj.seg_ent[sg + 1];
@@ -140,24 +137,19 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
         }
     }
 
-    // point sources of this tile (rare): per target node one owning thread
+    // point sources: every thread looks up its own nodes in the tile's dense map
     float src[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) src[q] = 0.0f;
     if (a.inject) {
-        const int64_t tile_id = ((int64_t)shot * ntz + bz) * ntx + bx;
-        const int sb = a.inj.tile_ptr[tile_id], se = a.inj.tile_ptr[tile_id + 1];
-        if (sb < se) {
+        const int map = a.inj.tile_dense[((int64_t)shot * ntz + bz) * ntx + bx];
+        if (map >= 0) {
+            const int32_t *dm = a.inj.dense + (int64_t)map * (T2X * T2Z) + (ly * NQ) * T2X + lx;
             const float *amp = a.amp.ptr + shot * a.amp.shot_stride + (int64_t)a.k * a.amp.k_stride;
-            for (int sg = sb; sg < se; ++sg) {
-                const int loc = a.inj.seg_local[sg];          // lz * 64 + lx of the target node
-                const float v = segment_value(a.inj, amp, a.amp.scale, sg);
-                const int lz = loc >> 6;
-                if ((loc & 63) == lx && lz / NQ == ly) {
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        if (lz - ly * NQ == q) src[q] += v;
-                }
+            for (int q = 0; q < NQ; ++q) {
+                const int sg = dm[q * T2X];
+                if (sg >= 0) src[q] = segment_value(a.inj, amp, a.amp.scale, sg);
             }
         }
     }
@@ -281,18 +273,13 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
         }
         float sa = 0.0f, sbv = 0.0f;   // point-source terms of this thread's two nodes
         if (a.inject) {
-            const int64_t tile_id = (((int64_t)shot * L.ntiles[2] + z) * nty + by) * ntx + bx;
-            const int s0 = a.inj.tile_ptr[tile_id], s1 = a.inj.tile_ptr[tile_id + 1];
-            if (s0 < s1) {
+            const int map = a.inj.tile_dense[(((int64_t)shot * L.ntiles[2] + z) * nty + by) * ntx + bx];
+            if (map >= 0) {
+                const int32_t *dm = a.inj.dense + (int64_t)map * (T3X * T3Y) + ly * T3X + lx;
                 const float *amp = a.amp.ptr + shot * a.amp.shot_stride + (int64_t)a.k * a.amp.k_stride;
-                for (int sg = s0; sg < s1; ++sg) {
-                    const int loc = a.inj.seg_local[sg];      // ly * 64 + lx within the plane tile
-                    const float v = segment_value(a.inj, amp, a.amp.scale, sg);
-                    if ((loc & 63) == lx) {
-                        if ((loc >> 6) == ly) sa += v;
-                        if ((loc >> 6) == ly + 4) sbv += v;
-                    }
-                }
+                const int ga = dm[0], gb = dm[4 * T3X];
+                if (ga >= 0) sa = segment_value(a.inj, amp, a.amp.scale, ga);
+                if (gb >= 0) sbv = segment_value(a.inj, amp, a.amp.scale, gb);
             }
         }
         __syncthreads();

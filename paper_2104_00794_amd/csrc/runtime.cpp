@@ -240,22 +240,6 @@ bool corners_of(const Problem &P, const tpx_grid *g, const double pos[3], Corner
     return true;
 }
 
-// Upper bounds used to size the table area independently of positions.
-struct TableCaps {
-    int64_t src_ent, rec_ent, tile_ptr, smp_rec, smp_src, nc;
-};
-
-TableCaps table_caps(const Problem &P) {
-    TableCaps t;
-    t.nc = P.L.ndim == 3 ? 8 : 4;
-    t.src_ent = (int64_t)P.L.S * t.nc;
-    t.rec_ent = (int64_t)P.L.S * P.nrec * t.nc;
-    t.tile_ptr = (int64_t)P.L.S * P.L.tiles_per_shot + 1;
-    t.smp_rec = (int64_t)P.L.S * P.nrec;
-    t.smp_src = P.L.S;
-    return t;
-}
-
 struct Blob {
     std::vector<unsigned char> bytes;
     size_t put(const void *p, size_t n) {
@@ -266,19 +250,8 @@ struct Blob {
     }
 };
 
-size_t inject_bytes(int64_t tile_ptr, int64_t ent) {
-    return align_up(tile_ptr * 4) + 3 * align_up(ent * 4) + align_up((ent + 1) * 4) + align_up(ent * 4);
-}
-size_t sample_bytes(int64_t n, int64_t nc) { return align_up(n * 4) + align_up(n * nc * 4); }
-
-size_t tables_bytes(const Problem &P) {
-    const TableCaps t = table_caps(P);
-    return inject_bytes(t.tile_ptr, t.src_ent) + inject_bytes(t.tile_ptr, t.rec_ent) + sample_bytes(t.smp_rec, t.nc) +
-           sample_bytes(t.smp_src, t.nc);
-}
-
 struct HostInject {  // offsets into the blob
-    size_t tile_ptr, seg_local, seg_ent, ent_idx, ent_w;
+    size_t tile_dense, dense, seg_ent, ent_idx, ent_w;
 };
 struct HostSample {
     size_t base, w;
@@ -292,6 +265,10 @@ struct Entry {
     float w;
 };
 
+// Injection tables: entries sorted by (tile, target node, source index); a
+// segment is the run of entries of one target node.  Every tile that has at
+// least one segment gets a dense map "node of the tile -> segment or -1", so a
+// step kernel finds the source term of each of its nodes with one load.
 HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
     const Layout &L = P.L;
     std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &c) {
@@ -300,23 +277,28 @@ HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
         return a.idx < c.idx;
     });
     const int64_t ntile = (int64_t)L.S * L.tiles_per_shot;
-    std::vector<int32_t> tile_ptr(ntile + 1, 0), seg_local, seg_ent, ent_idx;
+    const int64_t tp = (int64_t)L.tile[0] * L.tile[1] * L.tile[2];
+    std::vector<int32_t> tile_dense(ntile, -1), dense, seg_ent, ent_idx;
     std::vector<float> ent_w;
+    int32_t nseg = 0;
     for (size_t i = 0; i < ent.size(); ++i) {
-        const bool new_seg = i == 0 || ent[i].tile != ent[i - 1].tile || ent[i].local != ent[i - 1].local;
+        const bool new_tile = i == 0 || ent[i].tile != ent[i - 1].tile;
+        const bool new_seg = new_tile || ent[i].local != ent[i - 1].local;
+        if (new_tile) {
+            tile_dense[ent[i].tile] = (int32_t)(dense.size() / tp);
+            dense.resize(dense.size() + tp, -1);
+        }
         if (new_seg) {
-            seg_local.push_back(ent[i].local);
+            dense[(size_t)tile_dense[ent[i].tile] * tp + ent[i].local] = nseg++;
             seg_ent.push_back((int32_t)i);
-            tile_ptr[ent[i].tile + 1]++;
         }
         ent_idx.push_back(ent[i].idx);
         ent_w.push_back(ent[i].w);
     }
     seg_ent.push_back((int32_t)ent.size());
-    for (int64_t t = 0; t < ntile; ++t) tile_ptr[t + 1] += tile_ptr[t];
     HostInject h;
-    h.tile_ptr = b.put(tile_ptr.data(), tile_ptr.size() * 4);
-    h.seg_local = b.put(seg_local.data(), seg_local.size() * 4);
+    h.tile_dense = b.put(tile_dense.data(), tile_dense.size() * 4);
+    h.dense = b.put(dense.data(), dense.size() * 4);
     h.seg_ent = b.put(seg_ent.data(), seg_ent.size() * 4);
     h.ent_idx = b.put(ent_idx.data(), ent_idx.size() * 4);
     h.ent_w = b.put(ent_w.data(), ent_w.size() * 4);
@@ -420,7 +402,7 @@ tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     return TPX_OK;
 }
 
-Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr) {
+Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_bytes) {
     const Layout &L = P.L;
     Plan p;
     memset(&p, 0, sizeof p);
@@ -454,7 +436,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr) {
         p.res = take(ntr * 4);
         p.d = take(ntr * 4);
     }
-    p.tables = take(tables_bytes(P));
+    p.tables = take(table_bytes);
     p.total = o;
     return p;
 }
@@ -476,8 +458,8 @@ struct Ctx {
 
 InjectTables dev_inject(unsigned char *base, const HostInject &h) {
     InjectTables t;
-    t.tile_ptr = (const int32_t *)(base + h.tile_ptr);
-    t.seg_local = (const int32_t *)(base + h.seg_local);
+    t.tile_dense = (const int32_t *)(base + h.tile_dense);
+    t.dense = (const int32_t *)(base + h.dense);
     t.seg_ent = (const int32_t *)(base + h.seg_ent);
     t.ent_idx = (const int32_t *)(base + h.ent_idx);
     t.ent_w = (const float *)(base + h.ent_w);
@@ -556,17 +538,16 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     if (!m) return fail(TPX_E_INVAL, "model m must not be NULL");
     if (!geo->wavelet && (mode != M_ADJOINT && mode != M_BWD_PROBED))
         return fail(TPX_E_INVAL, "wavelet must not be NULL");
-    C.plan = make_plan(C.P, mode, pr);
+    Tables T;
+    st = build_tables(C.P, g, geo, &T);
+    if (st != TPX_OK) return st;
+    C.plan = make_plan(C.P, mode, pr, T.blob.bytes.size());
     if (!ws || ws_bytes < C.plan.total) {
         char buf[160];
         snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes,
                  C.plan.total);
         return fail(TPX_E_NOMEM, buf);
     }
-    Tables T;
-    st = build_tables(C.P, g, geo, &T);
-    if (st != TPX_OK) return st;
-    if (T.blob.bytes.size() > tables_bytes(C.P)) return fail(TPX_E_INVAL, "internal: geometry tables overflow");
     C.ws = (unsigned char *)ws;
     C.stream = (hipStream_t)stream;
     unsigned char *tb = C.ws + C.plan.tables;
@@ -923,7 +904,9 @@ size_t tpx_workspace_bytes(int32_t call, const tpx_grid *grid, const tpx_geom *g
         if (st != TPX_OK) return st;
         const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
         if (probed && (st = check_probe(P, probe)) != TPX_OK) return st;
-        out = make_plan(P, mode, probe).total;
+        Tables T;
+        if ((st = build_tables(P, grid, geom, &T)) != TPX_OK) return st;
+        out = make_plan(P, mode, probe, T.blob.bytes.size()).total;
         return TPX_OK;
     });
     return out;

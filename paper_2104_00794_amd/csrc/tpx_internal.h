@@ -62,14 +62,16 @@ struct Physics {
     float inv_nb;      // 1 / nbl (0 when nbl == 0)
 };
 
-// Point-source injection into one step: per (shot, tile) a list of target
-// points ("segments"), each with an ordered run of (source index, weight).
+// Point-source injection into one step.  A segment is the ordered run of
+// (source index, weight) entries of one target node.  tile_dense[tile] is -1
+// for a tile without sources, else the index of its dense map: dense[map *
+// nodes_per_tile + local node] = segment of that node or -1.
 struct InjectTables {
-    const int32_t *tile_ptr;  // [S * tiles_per_shot + 1] -> segment ranges
-    const int32_t *seg_local; // [nseg] local index within the tile
-    const int32_t *seg_ent;   // [nseg + 1] entry ranges (global, ascending)
-    const int32_t *ent_idx;   // [nent] source index (receiver id or 0)
-    const float *ent_w;       // [nent] interpolation weight
+    const int32_t *tile_dense; // [S * tiles_per_shot]
+    const int32_t *dense;      // [maps][nodes per tile]
+    const int32_t *seg_ent;    // [nseg + 1] entry ranges
+    const int32_t *ent_idx;    // [nent] source index (receiver id or 0)
+    const float *ent_w;        // [nent] interpolation weight
 };
 
 // Amplitudes injected at step k: amp[shot * shot_stride + k * k_stride + idx] * scale
