@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--probe", default=None, help="rademacher | gauss_b64")
     ap.add_argument("--block", type=int, default=0, help="time steps per probe contraction (0 = default)")
     ap.add_argument("--keep-vbar", action="store_true", help="accumulate vbar instead of folding it")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run the probe contractions on the auxiliary stream, overlapping the next time block")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (for HBM counter calibration)")
     ap.add_argument("--nt", type=int, default=None, help="override the record length (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-nt", type=int, default=0, help="time steps of the CPU-oracle sample (0 = full record)")
@@ -72,6 +76,16 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.copy_calibration:
+        n = 1 << 28  # 1 GiB of float32 read and 1 GiB written per copy
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
+        return
+    tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 1 if args.overlap else 0)
     if args.serving:
         return serving(args, dev)
 
@@ -176,6 +190,7 @@ def main():
         "config": {"workload": wl.name, "grid": "x".join(str(s) for s in wl.shape[::-1]), "h_m": wl.h,
                    "space_order": wl.order, "shots": S, "nt": nt, "nbl": wl.nbl, "r": r, "probe": kind,
                    "block": args.block or "default", "keep_vbar": bool(args.keep_vbar),
+                   "overlap_contractions": bool(tpx.get_option(tpx.OPT_OVERLAP_CONTRACTIONS)),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
         "host_enqueue_ms": round(host_enqueue_ms, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),

@@ -186,6 +186,16 @@ tpx_status tpx_job_advance(tpx_job *job, int32_t max_steps, void *stream, int32_
 tpx_status tpx_job_progress(const tpx_job *job, int64_t *steps_done, int64_t *steps_total);
 void tpx_job_destroy(tpx_job *job);
 
+/* Library-wide options.  TPX_OPT_OVERLAP_CONTRACTIONS (default 0): each
+ * time block's probe contraction runs on an auxiliary HIP stream owned by the
+ * library, concurrently with the next block of time steps, and is joined back
+ * into the caller's stream before the pass ends (the ring then holds 2b + 3
+ * instead of b + 2 slots).  The option changes workspace sizes: set it before
+ * sizing a workspace, not between sizing and use. */
+enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1 };
+tpx_status tpx_set_option(int32_t option, int64_t value);
+int64_t tpx_get_option(int32_t option);
+
 /* Device-side checks of the last call that used `ws`, after waiting for
  * `stream`: TPX_E_NUMERIC if the model held a non-finite or non-positive
  * value, TPX_E_CFL if it held a velocity above damp_vmax. */

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -373,13 +374,40 @@ tpx_status build_tables(const Problem &P, const tpx_grid *g, const tpx_geom *geo
 // workspace plan
 // ---------------------------------------------------------------------------
 
+// Library options (tpx_set_option).  Overlap: probe contractions run on an
+// auxiliary stream, concurrently with the next block of time steps.
+std::atomic<int> g_overlap{0};
+
+// Auxiliary streams, created on first use and kept for the process lifetime.
+std::mutex g_aux_mu;
+std::vector<hipStream_t> g_aux_free;
+
+hipError_t aux_acquire(hipStream_t *s) {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    if (!g_aux_free.empty()) {
+        *s = g_aux_free.back();
+        g_aux_free.pop_back();
+        return hipSuccess;
+    }
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+void aux_release(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_aux_mu);
+    g_aux_free.push_back(s);
+}
+
+// Ring slots for a time block of b steps: b + 2 when the contractions run in
+// stream order; 2 b + 3 when a block's contraction overlaps the next block.
+int ring_slots(int b, bool overlap) { return overlap ? 2 * b + 3 : b + 2; }
+
 // Time steps buffered per probe contraction: the accumulators' read-modify-
-// write costs 8 r / b bytes per point-step, the ring costs (b + 2) slots.
-int default_block(const Layout &L, int nt) {
+// write costs 8 r / b bytes per point-step, the ring costs ring_slots(b) slots.
+int default_block(const Layout &L, int nt, bool overlap) {
     const double slot_bytes = (double)L.slot_floats * 4.0;
     const double cap = 48e9;
     int b = 128;
-    while (b > 16 && (b + 2) * slot_bytes > cap) b /= 2;
+    while (b > 16 && ring_slots(b, overlap) * slot_bytes > cap) b /= 2;
     if (b > nt - 1) b = nt - 1;
     if (b < 1) b = 1;
     return b;
@@ -388,6 +416,7 @@ int default_block(const Layout &L, int nt) {
 struct Plan {
     size_t flags, parts, J, beta, ring, hist, Z, ubar, vbar, gpart, res, d, tables, total;
     int nslots, block;
+    bool overlap;
 };
 
 enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED };
@@ -408,10 +437,11 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     memset(&p, 0, sizeof p);
     const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
     const int r = probed ? pr->r : 0;
-    p.block = default_block(L, P.nt);
+    p.overlap = g_overlap.load() != 0 && mode != M_FORWARD && mode != M_ADJOINT;
+    p.block = default_block(L, P.nt, p.overlap);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
-    p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? 3 : p.block + 2;
+    p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? 3 : ring_slots(p.block, p.overlap);
     const size_t slot = (size_t)L.slot_floats * 4;
     const size_t ntr = (size_t)L.S * P.nt * P.nrec;
     size_t o = 0;
@@ -448,13 +478,53 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
 struct Ctx {
     Problem P;
     Plan plan;
-    unsigned char *ws;
-    hipStream_t stream;
+    unsigned char *ws = nullptr;
+    hipStream_t stream = nullptr;
     InjectTables src_inj, rec_inj;
     SampleTables rec_smp, src_smp;  // out/scales filled per use
-    float *beta;
-    float *ring;
+    float *beta = nullptr;
+    float *ring = nullptr;
+    // overlap of the contractions: auxiliary stream and per-block events
+    // (block i uses slot i & 1; the main stream waits for block i's
+    // contraction before block i + 2 starts overwriting its ring slots)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+
+    Ctx() = default;
+    Ctx(const Ctx &) = delete;
+    Ctx &operator=(const Ctx &) = delete;
+    ~Ctx() {
+        for (int i = 0; i < 2; ++i) {
+            if (ev_ready[i]) (void)hipEventDestroy(ev_ready[i]);
+            if (ev_done[i]) (void)hipEventDestroy(ev_done[i]);
+        }
+        if (aux) aux_release(aux);
+    }
 };
+
+// Hand a finished time block's contraction to the auxiliary stream.
+template <class F>
+tpx_status overlap_launch(Ctx &C, int block_idx, int kind, F &&launch) {
+    const int e = block_idx & 1;
+    TPX_HIP(hipEventRecord(C.ev_ready[e], C.stream));
+    TPX_HIP(hipStreamWaitEvent(C.aux, C.ev_ready[e], 0));
+    TPX_HIP(prof(kind, C.aux, launch));
+    TPX_HIP(hipEventRecord(C.ev_done[e], C.aux));
+    return TPX_OK;
+}
+
+// Before block `block_idx` overwrites ring slots: wait for the contraction of
+// block block_idx - 2 (same event slot).
+tpx_status overlap_guard(Ctx &C, int block_idx) {
+    if (block_idx >= 2) TPX_HIP(hipStreamWaitEvent(C.stream, C.ev_done[block_idx & 1], 0));
+    return TPX_OK;
+}
+
+// Join: the main stream waits for every contraction enqueued so far.
+tpx_status overlap_join(Ctx &C, int nblocks) {
+    if (nblocks >= 1) TPX_HIP(hipStreamWaitEvent(C.stream, C.ev_done[(nblocks - 1) & 1], 0));
+    return TPX_OK;
+}
 
 InjectTables dev_inject(unsigned char *base, const HostInject &h) {
     InjectTables t;
@@ -558,6 +628,13 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     C.src_smp = dev_sample(tb, T.src_smp);
     C.beta = (float *)(C.ws + C.plan.beta);
     C.ring = (float *)(C.ws + C.plan.ring);
+    if (C.plan.overlap) {
+        TPX_HIP(aux_acquire(&C.aux));
+        for (int i = 0; i < 2; ++i) {
+            TPX_HIP(hipEventCreateWithFlags(&C.ev_ready[i], hipEventDisableTiming));
+            TPX_HIP(hipEventCreateWithFlags(&C.ev_done[i], hipEventDisableTiming));
+        }
+    }
     TPX_HIP(fill_zero_p(C.ws + C.plan.flags, kAlign, C.stream));
     const float m_min = (float)(1.0 / (g->damp_vmax * g->damp_vmax) * (1.0 - 1e-5));
     TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
@@ -585,6 +662,7 @@ struct FwdLoop {
     float *ubar = nullptr;
     int k = 0;
     int s_lo = 1;
+    int blk = 0;   // index of the current time block
     bool finished = false;
 };
 
@@ -599,6 +677,7 @@ tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *
     f.ubar = ubar;
     f.k = 0;
     f.s_lo = 1;
+    f.blk = 0;
     f.finished = false;
     // u^{-1} = u^0 = 0: the first step reads slot 0 as both levels.  Other
     // slots are written before they are read, and ghost cells are never read.
@@ -630,21 +709,38 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
     int64_t n = 0;
     for (; f.k <= nt - 2 && n < max_steps; ++f.k, ++n) {
         const int k = f.k;
+        const int s = k + 1;
+        const bool ovl = f.Z && C.plan.overlap;
+        if (ovl && s == f.s_lo) {
+            tpx_status st = overlap_guard(C, f.blk);
+            if (st != TPX_OK) return st;
+        }
         a.k = k;
         a.cur = slot_ptr(f.buf, L, f.ns, k);
         a.prev = k == 0 ? a.cur : slot_ptr(f.buf, L, f.ns, k - 1);  // u^{-1} = u^0 = 0
         a.next = slot_ptr(f.buf, L, f.ns, k + 1);
         TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
-        const int s = k + 1;
         if (f.Z && (s - f.s_lo + 1 == C.plan.block || s == nt - 1)) {
             const int s_lo = f.s_lo;
-            TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream,
-                         [&] { return launch_accum_fwd(L, f.buf, f.ns, s_lo, s, f.Z, nt, f.r, f.ubar, C.stream); }));
+            if (ovl) {
+                tpx_status st = overlap_launch(C, f.blk, TPX_KERNEL_ACCUM_FWD, [&] {
+                    return launch_accum_fwd(L, f.buf, f.ns, s_lo, s, f.Z, nt, f.r, f.ubar, C.aux);
+                });
+                if (st != TPX_OK) return st;
+            } else {
+                TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream,
+                             [&] { return launch_accum_fwd(L, f.buf, f.ns, s_lo, s, f.Z, nt, f.r, f.ubar, C.stream); }));
+            }
             f.s_lo = s + 1;
+            ++f.blk;
         }
     }
     if (f.k > nt - 2 && !f.finished) {
         if (a.do_sample) TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(f.buf, L, f.ns, nt - 1), nt - 1, f.smp, C.stream); }));
+        if (f.Z && C.plan.overlap) {
+            tpx_status st = overlap_join(C, f.blk);
+            if (st != TPX_OK) return st;
+        }
         f.finished = true;
     }
     if (used) *used = n;
@@ -679,6 +775,7 @@ struct AdjLoop {
     AdjOut o;
     int k = 0;
     int s_hi = 0;
+    int blk = 0;   // index of the current time block
     bool finished = false;
 };
 
@@ -689,6 +786,7 @@ tpx_status adj_begin(Ctx &C, AdjLoop &b, const float *amp, const AdjOut &o) {
     b.o = o;
     b.k = nt - 1;
     b.s_hi = nt - 1;
+    b.blk = 0;
     b.finished = false;
     // lambda^{nt} = lambda^{nt-1} = 0; every other slot is written before it is read
     TPX_HIP(fill_zero_p(slot_ptr(C.ring, L, ns, nt), (size_t)L.slot_floats * 4, C.stream));
@@ -724,6 +822,11 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
     int64_t n = 0;
     for (; b.k >= 1 && n < max_steps; --b.k, ++n) {
         const int k = b.k;
+        const bool ovl = accum && C.plan.overlap;
+        if (ovl && k == b.s_hi) {
+            tpx_status st = overlap_guard(C, b.blk);
+            if (st != TPX_OK) return st;
+        }
         a.k = k;
         a.cur = slot_ptr(C.ring, L, ns, k);
         a.prev = slot_ptr(C.ring, L, ns, k + 1);
@@ -732,19 +835,29 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
         // lambda^{k-1} is known: w^k can be formed
         if (accum && (b.s_hi - k + 1 == C.plan.block || k == 1)) {
             const int s_hi = b.s_hi;
-            if (o.hist)
-                TPX_HIP(prof(TPX_KERNEL_ACCUM_FULL, C.stream,
-                             [&] { return launch_accum_full(L, o.hist, C.ring, ns, k, s_hi, o.gpart, C.stream); }));
-            else
-                TPX_HIP(prof(TPX_KERNEL_ACCUM_ADJ, C.stream, [&] {
-                    return launch_accum_adj(L, C.ring, ns, k, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c, o.vbar,
-                                            o.gpart, C.stream);
-                }));
+            hipStream_t cs = ovl ? C.aux : C.stream;
+            auto contract = [&] {
+                return o.hist ? launch_accum_full(L, o.hist, C.ring, ns, k, s_hi, o.gpart, cs)
+                              : launch_accum_adj(L, C.ring, ns, k, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c, o.vbar,
+                                                 o.gpart, cs);
+            };
+            const int kind = o.hist ? TPX_KERNEL_ACCUM_FULL : TPX_KERNEL_ACCUM_ADJ;
+            if (ovl) {
+                tpx_status st = overlap_launch(C, b.blk, kind, contract);
+                if (st != TPX_OK) return st;
+            } else {
+                TPX_HIP(prof(kind, C.stream, contract));
+            }
             b.s_hi = k - 1;
+            ++b.blk;
         }
     }
     if (b.k < 1 && !b.finished) {
         if (o.q_adj) TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, b.smp, C.stream); }));
+        if (accum && C.plan.overlap) {
+            tpx_status st = overlap_join(C, b.blk);
+            if (st != TPX_OK) return st;
+        }
         b.finished = true;
     }
     if (used) *used = n;
@@ -1105,6 +1218,19 @@ tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches) {
         *launches = n;
         return TPX_OK;
     });
+}
+
+tpx_status tpx_set_option(int32_t option, int64_t value) {
+    if (option == TPX_OPT_OVERLAP_CONTRACTIONS) {
+        g_overlap.store(value ? 1 : 0);
+        return TPX_OK;
+    }
+    return fail(TPX_E_INVAL, "unknown option");
+}
+
+int64_t tpx_get_option(int32_t option) {
+    if (option == TPX_OPT_OVERLAP_CONTRACTIONS) return g_overlap.load();
+    return -1;
 }
 
 tpx_status tpx_check_workspace(const void *ws, void *stream) {

@@ -94,6 +94,10 @@ def lib():
     L.tpx_job_progress.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64)]
     L.tpx_job_destroy.argtypes = [vp]
     L.tpx_job_destroy.restype = None
+    L.tpx_set_option.argtypes = [i32, ctypes.c_int64]
+    L.tpx_set_option.restype = ctypes.c_int
+    L.tpx_get_option.argtypes = [i32]
+    L.tpx_get_option.restype = ctypes.c_int64
     L.tpx_profile_enable.argtypes = [i32]
     L.tpx_profile_enable.restype = None
     L.tpx_profile_read.argtypes = [i32, P(ctypes.c_double), P(ctypes.c_int64)]
@@ -404,6 +408,16 @@ class Job:
 
 
 KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL = range(4)
+OPT_OVERLAP_CONTRACTIONS = 1
+
+
+def set_option(option: int, value: int):
+    """Library-wide option (changes workspace sizes: set before sizing)."""
+    _check(lib().tpx_set_option(int(option), int(value)))
+
+
+def get_option(option: int) -> int:
+    return int(lib().tpx_get_option(int(option)))
 
 
 def profile_enable(on: bool):

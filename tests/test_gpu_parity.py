@@ -310,3 +310,28 @@ def test_c3_full_grid_truncated_record():
     assert np.linalg.norm(g_o) > 0
     assert rel_l2(g_s, g_o) <= TOL
     assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
+def test_overlapped_contractions_are_bitwise_identical():
+    # contractions on the auxiliary stream (ring of 2b + 3 slots) give the same
+    # bits as in stream order: same kernels, same summation order
+    c = Case(small_2d(nz=30, nx=90, nt=170, nshots=2, nrec=11))
+    dobs = c.dobs_oracle()
+    probe = tpx.Probe(r=8, seed=4, block=16)
+    try:
+        tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 0)
+        a, Ja = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+        full0, _ = tpx.gradient_full(c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs))
+        tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 1)
+        b, Jb = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+        full1, _ = tpx.gradient_full(c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs))
+        job = tpx.Job(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+        while not job.advance(5):
+            pass
+        import torch
+        torch.cuda.synchronize()
+    finally:
+        tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 0)
+    assert np.array_equal(to_np(a), to_np(b)) and float(Ja.item()) == float(Jb.item())
+    assert np.array_equal(to_np(full0), to_np(full1))
+    assert np.array_equal(to_np(job.g), to_np(a))
