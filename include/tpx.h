@@ -207,10 +207,11 @@ tpx_status tpx_check_workspace(const void *ws, void *stream);
  * clears earlier records; tpx_profile_read waits for the recorded events and
  * returns the summed duration and the launch count of one kernel kind. */
 enum {
-    TPX_KERNEL_STEP = 0,      /* leapfrog step with fused injection/sampling */
-    TPX_KERNEL_ACCUM_FWD = 1, /* forward probe contraction                   */
-    TPX_KERNEL_ACCUM_ADJ = 2, /* adjoint probe contraction (or fold)         */
-    TPX_KERNEL_ACCUM_FULL = 3 /* full-history imaging term                   */
+    TPX_KERNEL_STEP = 0,      /* one leapfrog step with fused injection/sampling  */
+    TPX_KERNEL_ACCUM_FWD = 1, /* forward probe contraction                        */
+    TPX_KERNEL_ACCUM_ADJ = 2, /* adjoint probe contraction (or fold)              */
+    TPX_KERNEL_ACCUM_FULL = 3,/* full-history imaging term                        */
+    TPX_KERNEL_STEP2 = 4      /* two fused leapfrog steps in one launch (2D)      */
 };
 void tpx_profile_enable(int32_t on);
 tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches);

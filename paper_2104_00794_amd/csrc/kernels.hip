@@ -13,8 +13,13 @@ namespace tpx {
 // helpers
 // ---------------------------------------------------------------------------
 
+// The step kernels and their helpers pin every rounding: products are fused
+// only where an fmaf is written, so one- and two-step launches, fused and
+// separate sampling give bitwise identical results.
+
 // (distance into the absorbing layer / nbl)^2 along one axis, padded index I
 __device__ __forceinline__ float layer_frac2(int I, int nphys, int nb, float inv_nb) {
+#pragma clang fp contract(off)
     int into = 0;
     if (I < nb) into = nb - I;
     else if (I > nb + nphys - 1) into = I - (nb + nphys - 1);
@@ -25,8 +30,15 @@ __device__ __forceinline__ float layer_frac2(int I, int nphys, int nb, float inv
 // leapfrog update of the damped wave equation for one node:
 //   (1 + hd) next = 2 cur - (1 - hd) prev + beta (lap + src),  hd = d dt / 2
 __device__ __forceinline__ float leapfrog(float cur, float prev, float beta, float lap, float src, float hd) {
-    const float num = 2.0f * cur - (1.0f - hd) * prev + beta * (lap + src);
+#pragma clang fp contract(off)
+    const float num = __builtin_fmaf(beta, lap + src, __builtin_fmaf(-(1.0f - hd), prev, 2.0f * cur));
     return num * __builtin_amdgcn_rcpf(1.0f + hd);   // rcp(1) = 1 exactly in the interior
+}
+
+// The same update where hd == 0 (undamped interior): bitwise equal to leapfrog(..., 0).
+__device__ __forceinline__ float leapfrog0(float cur, float prev, float beta, float lap, float src) {
+#pragma clang fp contract(off)
+    return __builtin_fmaf(beta, lap + src, __builtin_fmaf(-1.0f, prev, 2.0f * cur));
 }
 
 // Sampling of `field` at this shot's points (receivers in the forward pass,
@@ -35,6 +47,7 @@ __device__ __forceinline__ float leapfrog(float cur, float prev, float beta, flo
 template <int NC>
 __device__ __forceinline__ void sample_points(const Layout &L, const float *field, int k, const SampleTables &smp,
                                               int shot, int64_t block_in_shot, int64_t blocks_per_shot) {
+#pragma clang fp contract(off)
     const int64_t G0 = L.G[0], plane = L.G[0] * L.G[1];
     for (int64_t i = block_in_shot * blockDim.x + threadIdx.x; i < smp.nsmp; i += blocks_per_shot * blockDim.x) {
         const int64_t e = (int64_t)shot * smp.nsmp + i;
@@ -52,25 +65,13 @@ __device__ __forceinline__ void sample_points(const Layout &L, const float *fiel
 
 // Source term of one target node: its entries summed in their stored order.
 __device__ __forceinline__ float segment_value(const InjectTables &inj, const float *a, float scale, int sg) {
+#pragma clang fp contract(off)
     float acc = 0.0f;
     const int e1 = inj.seg_ent[sg + 1];
     for (int e = inj.seg_ent[sg]; e < e1; ++e) acc += inj.ent_w[e] * a[inj.ent_idx[e]];
     return acc * scale;
 }
 
-// ---------------------------------------------------------------------------
-// 2D leapfrog step.  Block = 64 x 4 threads over a 64 (x) by 32 (z) tile of
-// outputs.  u^k is staged with its R-wide halo in LDS; every thread then owns
-// eight consecutive rows of one column: it reads its column (8 + 2R values)
-// from LDS once and keeps it in registers (z neighbours), and reads only the
-// x neighbours per output from LDS.  All global loads are issued before the
-// barrier, from clamped in-box addresses with the result selected, so no load
-// sits behind a branch.  Blocks are numbered XCD-aware: the hardware hands
-// block b to XCD b mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8
-// gives every XCD a contiguous run of tiles whose halos then hit in that XCD's
-// L2.  Only nodes of the padded box are read (outside it the field is zero),
-// so ghost cells of the buffers need no clearing.
-// ---------------------------------------------------------------------------
 __device__ __forceinline__ int xcd_logical_block(int nlogical) {
     const int per = (int)gridDim.x >> 3;
     const int hw = (int)blockIdx.x;
@@ -80,103 +81,245 @@ __device__ __forceinline__ int xcd_logical_block(int nlogical) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-template <int R>
-__global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph, const StepArgs a) {
-    constexpr int W = T2X + 2 * R;
-    constexpr int H = T2Z + 2 * R;
-    constexpr int NL = (H + 3) / 4;   // staged rows per thread
-    constexpr int NQ = T2Z / 4;       // outputs per thread (consecutive rows)
-    __shared__ float tile[H][W];
+// Raw buffer access: a descriptor per array (scalar registers), a 32-bit byte
+// offset per lane and a wave-uniform byte offset per row (scalar), so row
+// addressing costs no vector instructions.  Accesses past `bytes` read zero
+// and are not written; the kernels never make them.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const float *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
 
-    const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2];
-    const int lid = xcd_logical_block(ntx * ntz * L.S);
-    if (lid < 0) return;
-    const int bx = lid % ntx, bz = (lid / ntx) % ntz, shot = lid / (ntx * ntz);
-
-    const int tid = threadIdx.x;
-    const int lx = tid & 63, ly = tid >> 6;
-    const int x0 = bx * T2X, z0 = bz * T2Z;
+// ---------------------------------------------------------------------------
+// 2D leapfrog steps, one or two per launch.
+//
+// A block owns a tile of T2Z rows by TX = 64 - 2R columns; lane l of each wave
+// holds column x0 - R + l, so a wave row covers the tile plus an R-wide halo on
+// both sides.  u^k is staged in LDS with a 2R halo.  Every thread owns NQ
+// consecutive rows of one column and keeps that column in registers (z
+// neighbours); x neighbours come from LDS.
+//
+// One step: u^{k+1} on the tile.  Two steps (temporal blocking): u^{k+1} is
+// computed on the tile plus its R-wide halo (the extended region, stored in
+// LDS), then u^{k+2} on the tile; both are written.  The halo nodes of u^{k+1}
+// are recomputed by the neighbouring tiles with the same arithmetic, so the
+// result is bitwise that of two one-step launches, while u^{k-1}, u^k and beta
+// are read once for two steps.
+//
+// Tiles whose staged region lies in the padded box and whose extended region
+// is undamped take a path with no clamping, masking or damping terms.  Row
+// offsets are wave-uniform (scalar registers); lanes add a 32-bit column
+// offset.  Blocks are numbered XCD-aware: the hardware hands block b to XCD b
+// mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8 gives every XCD a
+// contiguous run of tiles whose halos then hit in that XCD's L2.
+// ---------------------------------------------------------------------------
+template <int R, int NSTEP, bool FAST>
+__device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot, int tile,
+                                            int x0, int z0, float (*U)[64 + 2 * R], float (*V)[64]) {
+#pragma clang fp contract(off)
+    constexpr int TX = t2x(R), TZ = T2Z;
+    constexpr int SH = TZ + 4 * R;            // staged rows of u^k
+    constexpr int NQ = TZ / 4;                // rows per thread
+    constexpr int NS = (SH + 3) / 4;          // staged rows per thread
+    constexpr int NH = NSTEP == 2 ? R / 2 : 0;   // extended-region halo rows per thread (2R rows / 4 waves)
+    constexpr int MAPN = 64 * (TZ + 2 * R);   // nodes of one injection map
+    const int lx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int G0 = (int)L.G[0], P0 = (int)L.P[0], P2 = (int)L.P[2];
-    const float *cur = a.cur + shot * L.shot_floats + XO;
-    const float *prev = a.prev + shot * L.shot_floats + XO;
-    const float *beta = a.beta + XO;
-    float *next = a.next + shot * L.shot_floats + XO;
+    const uint32_t span = (uint32_t)(L.shot_floats * 4);
+    const int64_t so = shot * L.shot_floats + XO;
+    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cur + so, span), rp = buf_rsrc(a.prev + so, span);
+    const __amdgpu_buffer_rsrc_t rb = buf_rsrc(a.beta + XO, span);
+    auto rowoff = [&](int z) { return (uint32_t)((z + R) * G0 * 4); };   // byte offset of padded row z
 
-    const int gx = x0 - R + lx, gx2 = gx + 64;
-    const bool xin = gx >= 0 && gx < P0, xin2 = lx < 2 * R && gx2 < P0;
-    const int gxc = clampi(gx, 0, P0 - 1), gxc2 = clampi(gx2, 0, P0 - 1);
-    float t[NL], t2[NL];
+    // stage u^k, rows z0 - 2R .. z0 + TZ + 2R - 1, columns x0 - 2R .. x0 + TX + 2R - 1
+    const int sx = x0 - 2 * R + lx, sx2 = sx + 64;
+    const bool sxin = sx >= 0 && sx < P0, sxin2 = lx < 2 * R && sx2 < P0;
+    const uint32_t ox1 = 4u * (uint32_t)(FAST ? sx : clampi(sx, 0, P0 - 1));
+    const uint32_t ox2 = 4u * (uint32_t)(FAST ? (lx < 2 * R ? sx2 : sx) : clampi(sx2, 0, P0 - 1));
+    float t[NS], t2[NS];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int row = ly + 4 * i, gz = z0 - R + row;
-        const bool zin = row < H && gz >= 0 && gz < P2;
-        const int ro = (clampi(gz, 0, P2 - 1) + R) * G0;
-        const float v = cur[ro + gxc];
-        t[i] = (zin && xin) ? v : 0.0f;
-        t2[i] = (zin && xin2) ? cur[ro + gxc2] : 0.0f;
+    for (int i = 0; i < NS; ++i) {
+        const int row = w + 4 * i, gz = z0 - 2 * R + row;
+        const bool zin = FAST || (row < SH && gz >= 0 && gz < P2);
+        const uint32_t ro = rowoff(FAST ? (row < SH ? gz : z0) : clampi(gz, 0, P2 - 1));
+        const float v1 = buf_load(rc, ox1, ro), v2 = buf_load(rc, ox2, ro);
+        t[i] = (zin && (FAST || sxin)) ? v1 : 0.0f;
+        t2[i] = (zin && (FAST || sxin2)) ? v2 : 0.0f;
     }
-    const int x = x0 + lx, zb = z0 + ly * NQ;
-    const bool xo = x < P0;
-    const int xc = xo ? x : P0 - 1;
+    // u^{k-1} and beta at this thread's nodes: column x, rows zb .. zb + NQ - 1
+    const int x = x0 - R + lx;
+    const bool xin = x >= 0 && x < P0;
+    const uint32_t ox = 4u * (uint32_t)(FAST ? x : clampi(x, 0, P0 - 1));
+    const int zb = z0 + w * NQ;
     float p[NQ], b[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int z = zb + q;
-        const int off = (clampi(z, 0, P2 - 1) + R) * G0 + xc;
-        const float pv = prev[off], bv = beta[off];
-        const bool ok = xo && z < P2;
+        const uint32_t ro = rowoff(FAST ? z : clampi(z, 0, P2 - 1));
+        const float pv = buf_load(rp, ox, ro), bv = buf_load(rb, ox, ro);
+        const bool ok = FAST || (xin && z < P2);
         p[q] = ok ? pv : 0.0f;
         b[q] = ok ? bv : 0.0f;
     }
+    // the same at the extended region's halo rows (two steps)
+    float hp[NH > 0 ? NH : 1], hb[NH > 0 ? NH : 1];
 #pragma unroll
-    for (int i = 0; i < NL; ++i) {
-        const int row = ly + 4 * i;
-        if (row < H) {
-            tile[row][lx] = t[i];
-            if (lx < 2 * R) tile[row][64 + lx] = t2[i];
+    for (int i = 0; i < NH; ++i) {
+        const int hr = w + 4 * i;   // 0 .. 2R-1
+        const int z = hr < R ? z0 - R + hr : z0 + TZ + (hr - R);
+        const uint32_t ro = rowoff(FAST ? z : clampi(z, 0, P2 - 1));
+        const float pv = buf_load(rp, ox, ro), bv = buf_load(rb, ox, ro);
+        const bool ok = FAST || (xin && z >= 0 && z < P2);
+        hp[i] = ok ? pv : 0.0f;
+        hb[i] = ok ? bv : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int row = w + 4 * i;
+        if (row < SH) {
+            U[row][lx] = t[i];
+            if (lx < 2 * R) U[row][64 + lx] = t2[i];
         }
     }
 
-    // point sources: every thread looks up its own nodes in the tile's dense map
-    float src[NQ];
+    // point sources: each node looks up its segment in the tile's dense map
+    float s1[NQ], s2[NQ], sh[NH > 0 ? NH : 1];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) src[q] = 0.0f;
+    for (int q = 0; q < NQ; ++q) s1[q] = s2[q] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NH; ++i) sh[i] = 0.0f;
     if (a.inject) {
-        const int map = a.inj.tile_dense[((int64_t)shot * ntz + bz) * ntx + bx];
+        const int map = a.inj.tile_dense[tile];
         if (map >= 0) {
-            const int32_t *dm = a.inj.dense + (int64_t)map * (T2X * T2Z) + (ly * NQ) * T2X + lx;
-            const float *amp = a.amp.ptr + shot * a.amp.shot_stride + (int64_t)a.k * a.amp.k_stride;
+            const int32_t *dm = a.inj.dense + (int64_t)map * MAPN + lx;
+            const float *amp = a.amp.ptr + shot * a.amp.shot_stride;
+            const float *amp1 = amp + (int64_t)a.k * a.amp.k_stride;
+            const float *amp2 = amp + (int64_t)a.k2 * a.amp.k_stride;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                const int sg = dm[q * T2X];
-                if (sg >= 0) src[q] = segment_value(a.inj, amp, a.amp.scale, sg);
+                const int sg = dm[(w * NQ + q + R) * 64];
+                if (sg >= 0) {
+                    s1[q] = segment_value(a.inj, amp1, a.amp.scale, sg);
+                    if (NSTEP == 2) s2[q] = segment_value(a.inj, amp2, a.amp.scale, sg);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                const int hr = w + 4 * i;
+                const int sg = dm[(hr < R ? hr : TZ + hr) * 64];
+                if (sg >= 0) sh[i] = segment_value(a.inj, amp1, a.amp.scale, sg);
             }
         }
     }
     __syncthreads();
 
-    float col[NQ + 2 * R];
+    // first step on this thread's rows
+    const float hx = FAST ? 0.0f : layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
+    const bool act = lx >= R && lx < R + TX && (FAST || x < P0);   // lanes on tile columns
+    const __amdgpu_buffer_rsrc_t rn1 = buf_rsrc(a.next + so, span);
+    float c[NQ], hd[NQ];
+    {
+        float col[NQ + 2 * R];
 #pragma unroll
-    for (int i = 0; i < NQ + 2 * R; ++i) col[i] = tile[ly * NQ + i][lx + R];
-    const float hx = layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
+        for (int i = 0; i < NQ + 2 * R; ++i) col[i] = U[w * NQ + R + i][lx + R];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int z = zb + q, lr = ly * NQ + q + R;
-        const float c = col[q + R];
-        float lap = 2.0f * ph.c[0] * c;
+        for (int q = 0; q < NQ; ++q) {
+            const int z = zb + q, ur = w * NQ + q + 2 * R;
+            const float cv = col[q + R];
+            float lap = 2.0f * ph.c[0] * cv;
 #pragma unroll
-        for (int k = 1; k <= R; ++k)
-            lap += ph.c[k] * ((tile[lr][lx + R - k] + tile[lr][lx + R + k]) + (col[q + R - k] + col[q + R + k]));
-        if (z < P2 && xo) {
-            const float hd = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
-            next[(z + R) * G0 + x] = leapfrog(c, p[q], b[q], lap, src[q], hd);
+            for (int k = 1; k <= R; ++k)
+                lap = __builtin_fmaf(ph.c[k], (U[ur][lx + R - k] + U[ur][lx + R + k]) + (col[q + R - k] + col[q + R + k]),
+                                     lap);
+            float v;
+            if (FAST) {
+                v = leapfrog0(cv, p[q], b[q], lap, s1[q]);
+            } else {
+                hd[q] = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
+                v = (xin && z < P2) ? leapfrog(cv, p[q], b[q], lap, s1[q], hd[q]) : 0.0f;
+            }
+            if (NSTEP == 1) {
+                if (act && (FAST || z < P2)) buf_store(v, rn1, ox, rowoff(z));
+            } else {
+                V[w * NQ + q + R][lx] = v;
+            }
+            c[q] = cv;
         }
     }
+    if (NSTEP == 1) return;
 
-    if (a.do_sample) {
-        const int per_shot = ntx * ntz;
-        sample_points<4>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bz * ntx + bx, per_shot);
+    // first step on the extended region's halo rows
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const int hr = w + 4 * i;
+        const int z = hr < R ? z0 - R + hr : z0 + TZ + (hr - R);
+        const int ur = z - z0 + 2 * R;
+        const float cv = U[ur][lx + R];
+        float lap = 2.0f * ph.c[0] * cv;
+#pragma unroll
+        for (int k = 1; k <= R; ++k)
+            lap = __builtin_fmaf(ph.c[k], (U[ur][lx + R - k] + U[ur][lx + R + k]) + (U[ur - k][lx + R] + U[ur + k][lx + R]),
+                                 lap);
+        float v;
+        if (FAST) {
+            v = leapfrog0(cv, hp[i], hb[i], lap, sh[i]);
+        } else {
+            const float h = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
+            v = (xin && z >= 0 && z < P2) ? leapfrog(cv, hp[i], hb[i], lap, sh[i], h) : 0.0f;
+        }
+        V[hr < R ? hr : TZ + hr][lx] = v;
     }
+    __syncthreads();
+
+    // second step on the tile
+    const __amdgpu_buffer_rsrc_t rn2 = buf_rsrc(a.next2 + so, span);
+    float col[NQ + 2 * R];
+#pragma unroll
+    for (int i = 0; i < NQ + 2 * R; ++i) col[i] = V[w * NQ + i][lx];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int z = zb + q, vr = w * NQ + q + R;
+        const float v = col[q + R];
+        float lap = 2.0f * ph.c[0] * v;
+#pragma unroll
+        for (int k = 1; k <= R; ++k) {
+            const int xl = lx - k < 0 ? 0 : lx - k, xr = lx + k > 63 ? 63 : lx + k;   // in-range reads for idle lanes
+            lap = __builtin_fmaf(ph.c[k], (V[vr][xl] + V[vr][xr]) + (col[q + R - k] + col[q + R + k]), lap);
+        }
+        if (act && (FAST || z < P2)) {
+            const uint32_t ro = rowoff(z);
+            buf_store(v, rn1, ox, ro);
+            buf_store(FAST ? leapfrog0(v, c[q], b[q], lap, s2[q]) : leapfrog(v, c[q], b[q], lap, s2[q], hd[q]), rn2, ox, ro);
+        }
+    }
+}
+
+template <int R, int NSTEP>
+__global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph, const StepArgs a) {
+    constexpr int TX = t2x(R), TZ = T2Z;
+    __shared__ float U[TZ + 4 * R][64 + 2 * R];
+    __shared__ float V[NSTEP == 2 ? TZ + 2 * R : 1][64];
+    const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2];
+    const int lid = xcd_logical_block(ntx * ntz * L.S);
+    if (lid < 0) return;
+    const int bx = lid % ntx, bz = (lid / ntx) % ntz, shot = lid / (ntx * ntz);
+    const int x0 = bx * TX, z0 = bz * TZ, nb = L.nb;
+    const bool fast = x0 - 2 * R >= 0 && z0 - 2 * R >= 0 && x0 + TX + 2 * R <= (int)L.P[0] &&
+                      z0 + TZ + 2 * R <= (int)L.P[2] && x0 - R >= nb && z0 - R >= nb &&
+                      x0 + TX + R <= nb + (int)L.n[0] && z0 + TZ + R <= nb + (int)L.n[2];
+    const int tile = (shot * ntz + bz) * ntx + bx;
+    if (fast) step2d_body<R, NSTEP, true>(L, ph, a, shot, tile, x0, z0, U, V);
+    else step2d_body<R, NSTEP, false>(L, ph, a, shot, tile, x0, z0, U, V);
+
+    const int per_shot = ntx * ntz;
+    if (a.do_sample) sample_points<4>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bz * ntx + bx, per_shot);
+    if (a.sample_prev) sample_points<4>(L, a.prev + shot * L.shot_floats, a.kp, a.smp, shot, bz * ntx + bx, per_shot);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,6 +333,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
 // ---------------------------------------------------------------------------
 template <int R>
 __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
+#pragma clang fp contract(off)
     constexpr int W = T3X + 2 * R;
     constexpr int H = T3Y + 2 * R;   // 16 rows for R = 4
     __shared__ float plane_t[2][H][W];
@@ -288,10 +432,12 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
         float lapa = 3.0f * ph.c[0] * qa[R], lapb = 3.0f * ph.c[0] * qb[R];
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
-            lapa += ph.c[k] * ((pt[R + ly][R + lx - k] + pt[R + ly][R + lx + k]) +
-                               (pt[R + ly - k][R + lx] + pt[R + ly + k][R + lx]) + (qa[R - k] + qa[R + k]));
-            lapb += ph.c[k] * ((pt[R + 4 + ly][R + lx - k] + pt[R + 4 + ly][R + lx + k]) +
-                               (pt[R + 4 + ly - k][R + lx] + pt[R + 4 + ly + k][R + lx]) + (qb[R - k] + qb[R + k]));
+            lapa = __builtin_fmaf(ph.c[k], (pt[R + ly][R + lx - k] + pt[R + ly][R + lx + k]) +
+                                               (pt[R + ly - k][R + lx] + pt[R + ly + k][R + lx]) + (qa[R - k] + qa[R + k]),
+                                  lapa);
+            lapb = __builtin_fmaf(ph.c[k], (pt[R + 4 + ly][R + lx - k] + pt[R + 4 + ly][R + lx + k]) +
+                                               (pt[R + 4 + ly - k][R + lx] + pt[R + 4 + ly + k][R + lx]) + (qb[R - k] + qb[R + k]),
+                                  lapb);
         }
         const float hz = layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb);
         if (oa) next[zo + cola] = leapfrog(qa[R], pa, ba, lapa, sa, ph.hd_max * (hxy_a + hz));
@@ -303,10 +449,9 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
         }
     }
 
-    if (a.do_sample) {
-        const int per_shot = ntx * nty * nzc;
-        sample_points<8>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, (zc * nty + by) * ntx + bx, per_shot);
-    }
+    const int per_shot = ntx * nty * nzc, bis = (zc * nty + by) * ntx + bx;
+    if (a.do_sample) sample_points<8>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bis, per_shot);
+    if (a.sample_prev) sample_points<8>(L, a.prev + shot * L.shot_floats, a.kp, a.smp, shot, bis, per_shot);
 }
 
 template <int NC>
@@ -319,9 +464,15 @@ hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hi
     if (L.ndim == 2) {
         const int64_t nlog = L.ntiles[0] * L.ntiles[2] * L.S;
         dim3 grid((unsigned)((nlog + 7) / 8 * 8));
-        if (L.R == 2) hipLaunchKernelGGL(k_step2d<2>, grid, dim3(256), 0, stream, L, ph, a);
-        else hipLaunchKernelGGL(k_step2d<4>, grid, dim3(256), 0, stream, L, ph, a);
+        if (a.nstep == 2) {
+            if (L.R == 2) hipLaunchKernelGGL((k_step2d<2, 2>), grid, dim3(256), 0, stream, L, ph, a);
+            else hipLaunchKernelGGL((k_step2d<4, 2>), grid, dim3(256), 0, stream, L, ph, a);
+        } else {
+            if (L.R == 2) hipLaunchKernelGGL((k_step2d<2, 1>), grid, dim3(256), 0, stream, L, ph, a);
+            else hipLaunchKernelGGL((k_step2d<4, 1>), grid, dim3(256), 0, stream, L, ph, a);
+        }
     } else {
+        if (a.nstep != 1) return hipErrorInvalidValue;
         const int64_t zchunks = (L.P[2] + T3Z - 1) / T3Z;
         const int64_t nlog = L.ntiles[0] * L.ntiles[1] * zchunks * L.S;
         dim3 grid((unsigned)((nlog + 7) / 8 * 8));

@@ -178,10 +178,16 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
     L.nphys = L.n[0] * L.n[1] * L.n[2];
     L.npad = L.P[0] * L.P[1] * L.P[2];
     if (L.shot_floats >= (int64_t)1 << 31) return fail(TPX_E_INVAL, "one shot's field exceeds 2^31 floats");
+    // the 2D step kernels address one shot's field with 32-bit byte offsets
+    if (L.ndim == 2 && L.shot_floats >= (int64_t)1 << 30) return fail(TPX_E_INVAL, "one 2D shot field exceeds 2^30 floats");
     if (L.ndim == 2) {
-        L.tile[0] = T2X; L.tile[1] = 1; L.tile[2] = T2Z;
+        L.tile[0] = t2x(L.R); L.tile[1] = 1; L.tile[2] = T2Z;
+        L.map[0] = 64; L.map[1] = 1; L.map[2] = T2Z + 2 * L.R;
+        L.map_org[0] = -L.R; L.map_org[1] = 0; L.map_org[2] = -L.R;
     } else {
         L.tile[0] = T3X; L.tile[1] = T3Y; L.tile[2] = 1;
+        L.map[0] = T3X; L.map[1] = T3Y; L.map[2] = 1;
+        L.map_org[0] = L.map_org[1] = L.map_org[2] = 0;
     }
     for (int a = 0; a < 3; ++a) L.ntiles[a] = (L.P[a] + L.tile[a] - 1) / L.tile[a];
     L.tiles_per_shot = L.ntiles[0] * L.ntiles[1] * L.ntiles[2];
@@ -275,10 +281,11 @@ HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
     std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &c) {
         if (a.tile != c.tile) return a.tile < c.tile;
         if (a.local != c.local) return a.local < c.local;
-        return a.idx < c.idx;
+        if (a.idx != c.idx) return a.idx < c.idx;
+        return a.w < c.w;
     });
     const int64_t ntile = (int64_t)L.S * L.tiles_per_shot;
-    const int64_t tp = (int64_t)L.tile[0] * L.tile[1] * L.tile[2];
+    const int64_t tp = (int64_t)L.map[0] * L.map[1] * L.map[2];
     std::vector<int32_t> tile_dense(ntile, -1), dense, seg_ent, ent_idx;
     std::vector<float> ent_w;
     int32_t nseg = 0;
@@ -306,18 +313,37 @@ HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
     return h;
 }
 
+// Tiles t along one axis whose map [t * tile + org, t * tile + org + extent)
+// contains padded index i.
+void tiles_covering(int64_t i, int tile, int org, int extent, int64_t ntiles, int64_t *lo, int64_t *hi) {
+    // t * tile <= i - org  and  t * tile > i - org - extent
+    const int64_t a = i - org - extent + 1, b = i - org;
+    *lo = a <= 0 ? 0 : (a + tile - 1) / tile;
+    *hi = b < 0 ? -1 : b / tile;
+    if (*hi > ntiles - 1) *hi = ntiles - 1;
+}
+
+// One entry per (tile whose map contains the corner node, corner).
 void push_corners(const Problem &P, const Corners &c, int shot, int idx, std::vector<Entry> &ent) {
     const Layout &L = P.L;
     for (int i = 0; i < c.cnt; ++i) {
         if (c.w[i] == 0.0) continue;  // contributes exactly nothing
-        const int64_t tx = c.ix[i] / L.tile[0], ty = c.iy[i] / L.tile[1], tz = c.iz[i] / L.tile[2];
-        Entry e;
-        e.tile = (((int64_t)shot * L.ntiles[2] + tz) * L.ntiles[1] + ty) * L.ntiles[0] + tx;
-        e.local = (int32_t)((((c.iz[i] % L.tile[2]) * L.tile[1]) + (c.iy[i] % L.tile[1])) * L.tile[0] +
-                            (c.ix[i] % L.tile[0]));
-        e.idx = idx;
-        e.w = (float)c.w[i];
-        ent.push_back(e);
+        const int64_t pos[3] = {c.ix[i], c.iy[i], c.iz[i]};
+        int64_t lo[3], hi[3];
+        for (int d = 0; d < 3; ++d) tiles_covering(pos[d], L.tile[d], L.map_org[d], L.map[d], L.ntiles[d], &lo[d], &hi[d]);
+        for (int64_t tz = lo[2]; tz <= hi[2]; ++tz)
+            for (int64_t ty = lo[1]; ty <= hi[1]; ++ty)
+                for (int64_t tx = lo[0]; tx <= hi[0]; ++tx) {
+                    const int64_t mx = pos[0] - (tx * L.tile[0] + L.map_org[0]);
+                    const int64_t my = pos[1] - (ty * L.tile[1] + L.map_org[1]);
+                    const int64_t mz = pos[2] - (tz * L.tile[2] + L.map_org[2]);
+                    Entry e;
+                    e.tile = (((int64_t)shot * L.ntiles[2] + tz) * L.ntiles[1] + ty) * L.ntiles[0] + tx;
+                    e.local = (int32_t)((mz * L.map[1] + my) * L.map[0] + mx);
+                    e.idx = idx;
+                    e.w = (float)c.w[i];
+                    ent.push_back(e);
+                }
     }
 }
 
@@ -441,7 +467,10 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     p.block = default_block(L, P.nt, p.overlap);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
-    p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? 3 : ring_slots(p.block, p.overlap);
+    // without contractions the ring holds the levels one launch touches: three,
+    // four for two fused steps (2D).  With contractions a launch never crosses a
+    // block end, so one block plus two levels suffices.
+    p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? (P.L.ndim == 2 ? 4 : 3) : ring_slots(p.block, p.overlap);
     const size_t slot = (size_t)L.slot_floats * 4;
     const size_t ntr = (size_t)L.S * P.nt * P.nrec;
     size_t o = 0;
@@ -655,6 +684,7 @@ float *slot_ptr(float *base, const Layout &L, int nslots, int k) {
 struct FwdLoop {
     StepArgs a;
     SampleTables smp;
+    bool sample = false;  // traces requested
     float *buf = nullptr;
     int ns = 0;
     const float *Z = nullptr;
@@ -662,9 +692,15 @@ struct FwdLoop {
     float *ubar = nullptr;
     int k = 0;
     int s_lo = 1;
+    int next_row = 0;  // first trace row not sampled yet
     int blk = 0;   // index of the current time block
     bool finished = false;
 };
+
+// Two fused steps are used in 2D whenever both steps fall in the caller's
+// budget and in one contraction block (the ring holds one block plus the two
+// levels around it).  They are skipped when contractions overlap the steps.
+bool two_steps_allowed(const Ctx &C) { return C.P.L.ndim == 2 && !C.plan.overlap; }
 
 tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
                      float *ubar) {
@@ -677,6 +713,7 @@ tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *
     f.ubar = ubar;
     f.k = 0;
     f.s_lo = 1;
+    f.next_row = 0;
     f.blk = 0;
     f.finished = false;
     // u^{-1} = u^0 = 0: the first step reads slot 0 as both levels.  Other
@@ -697,7 +734,7 @@ tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *
     f.smp.out_shot_stride = (int64_t)nt * C.P.nrec;
     f.smp.out_k_stride = C.P.nrec;
     f.smp.scale = 1.0f;
-    a.do_sample = (d && f.smp.nsmp > 0) ? 1 : 0;
+    f.sample = d && f.smp.nsmp > 0;
     a.smp = f.smp;
     return TPX_OK;
 }
@@ -707,36 +744,54 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
     const int nt = C.P.nt;
     StepArgs &a = f.a;
     int64_t n = 0;
-    for (; f.k <= nt - 2 && n < max_steps; ++f.k, ++n) {
+    while (f.k <= nt - 2 && n < max_steps) {
         const int k = f.k;
         const int s = k + 1;
         const bool ovl = f.Z && C.plan.overlap;
+        const bool block_end1 = f.Z && (s - f.s_lo + 1 == C.plan.block || s == nt - 1);
+        const int nstep = (two_steps_allowed(C) && k + 1 <= nt - 2 && n + 2 <= max_steps && !block_end1) ? 2 : 1;
         if (ovl && s == f.s_lo) {
             tpx_status st = overlap_guard(C, f.blk);
             if (st != TPX_OK) return st;
         }
+        a.nstep = nstep;
         a.k = k;
+        a.k2 = k + 1;
+        a.kp = k - 1;
         a.cur = slot_ptr(f.buf, L, f.ns, k);
         a.prev = k == 0 ? a.cur : slot_ptr(f.buf, L, f.ns, k - 1);  // u^{-1} = u^0 = 0
         a.next = slot_ptr(f.buf, L, f.ns, k + 1);
-        TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
-        if (f.Z && (s - f.s_lo + 1 == C.plan.block || s == nt - 1)) {
+        a.next2 = nstep == 2 ? slot_ptr(f.buf, L, f.ns, k + 2) : nullptr;
+        // sample every level read here that is not sampled yet
+        a.do_sample = f.sample && f.next_row <= k;
+        a.sample_prev = f.sample && k >= 1 && f.next_row <= k - 1;
+        if (f.sample) f.next_row = k + 1;
+        const int kind = nstep == 2 ? TPX_KERNEL_STEP2 : TPX_KERNEL_STEP;
+        TPX_HIP(prof(kind, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
+        f.k += nstep;
+        n += nstep;
+        const int s_last = k + nstep;  // last level written
+        if (f.Z && (s_last - f.s_lo + 1 == C.plan.block || s_last == nt - 1)) {
             const int s_lo = f.s_lo;
+            const int s_hi = s_last;
             if (ovl) {
                 tpx_status st = overlap_launch(C, f.blk, TPX_KERNEL_ACCUM_FWD, [&] {
-                    return launch_accum_fwd(L, f.buf, f.ns, s_lo, s, f.Z, nt, f.r, f.ubar, C.aux);
+                    return launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, C.aux);
                 });
                 if (st != TPX_OK) return st;
             } else {
                 TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream,
-                             [&] { return launch_accum_fwd(L, f.buf, f.ns, s_lo, s, f.Z, nt, f.r, f.ubar, C.stream); }));
+                             [&] { return launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, C.stream); }));
             }
-            f.s_lo = s + 1;
+            f.s_lo = s_hi + 1;
             ++f.blk;
         }
     }
     if (f.k > nt - 2 && !f.finished) {
-        if (a.do_sample) TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(f.buf, L, f.ns, nt - 1), nt - 1, f.smp, C.stream); }));
+        for (; f.sample && f.next_row <= nt - 1; ++f.next_row) {
+            const int row = f.next_row;
+            TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(f.buf, L, f.ns, row), row, f.smp, C.stream); }));
+        }
         if (f.Z && C.plan.overlap) {
             tpx_status st = overlap_join(C, f.blk);
             if (st != TPX_OK) return st;
@@ -775,6 +830,7 @@ struct AdjLoop {
     AdjOut o;
     int k = 0;
     int s_hi = 0;
+    int next_row = 0;  // highest sample row not sampled yet
     int blk = 0;   // index of the current time block
     bool finished = false;
 };
@@ -786,6 +842,7 @@ tpx_status adj_begin(Ctx &C, AdjLoop &b, const float *amp, const AdjOut &o) {
     b.o = o;
     b.k = nt - 1;
     b.s_hi = nt - 1;
+    b.next_row = nt - 1;
     b.blk = 0;
     b.finished = false;
     // lambda^{nt} = lambda^{nt-1} = 0; every other slot is written before it is read
@@ -807,7 +864,6 @@ tpx_status adj_begin(Ctx &C, AdjLoop &b, const float *amp, const AdjOut &o) {
     b.smp.out_shot_stride = nt;
     b.smp.out_k_stride = 1;
     b.smp.scale = (float)(C.P.dt * C.P.dt);
-    a.do_sample = o.q_adj ? 1 : 0;
     a.smp = b.smp;
     return TPX_OK;
 }
@@ -820,26 +876,40 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
     StepArgs &a = b.a;
     const bool accum = o.Z || o.hist;
     int64_t n = 0;
-    for (; b.k >= 1 && n < max_steps; --b.k, ++n) {
+    while (b.k >= 1 && n < max_steps) {
         const int k = b.k;
         const bool ovl = accum && C.plan.overlap;
+        const bool block_end1 = accum && (b.s_hi - k + 1 == C.plan.block || k == 1);
+        const int nstep = (two_steps_allowed(C) && k - 1 >= 1 && n + 2 <= max_steps && !block_end1) ? 2 : 1;
         if (ovl && k == b.s_hi) {
             tpx_status st = overlap_guard(C, b.blk);
             if (st != TPX_OK) return st;
         }
+        a.nstep = nstep;
         a.k = k;
+        a.k2 = k - 1;
+        a.kp = k + 1;
         a.cur = slot_ptr(C.ring, L, ns, k);
         a.prev = slot_ptr(C.ring, L, ns, k + 1);
         a.next = slot_ptr(C.ring, L, ns, k - 1);
-        TPX_HIP(prof(TPX_KERNEL_STEP, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
-        // lambda^{k-1} is known: w^k can be formed
-        if (accum && (b.s_hi - k + 1 == C.plan.block || k == 1)) {
+        a.next2 = nstep == 2 ? slot_ptr(C.ring, L, ns, k - 2) : nullptr;
+        // sample every level read here that is not sampled yet (rows nt-1 .. 0)
+        const bool smp = o.q_adj != nullptr;
+        a.do_sample = smp && b.next_row >= k;
+        a.sample_prev = smp && k + 1 <= nt - 1 && b.next_row >= k + 1;
+        if (smp) b.next_row = k - 1;
+        const int skind = nstep == 2 ? TPX_KERNEL_STEP2 : TPX_KERNEL_STEP;
+        TPX_HIP(prof(skind, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
+        b.k -= nstep;
+        n += nstep;
+        const int k_last = k - nstep + 1;  // last step taken: lambda^{k_last - 1} is known, w^{k_last} can be formed
+        if (accum && (b.s_hi - k_last + 1 == C.plan.block || k_last == 1)) {
             const int s_hi = b.s_hi;
             hipStream_t cs = ovl ? C.aux : C.stream;
             auto contract = [&] {
-                return o.hist ? launch_accum_full(L, o.hist, C.ring, ns, k, s_hi, o.gpart, cs)
-                              : launch_accum_adj(L, C.ring, ns, k, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c, o.vbar,
-                                                 o.gpart, cs);
+                return o.hist ? launch_accum_full(L, o.hist, C.ring, ns, k_last, s_hi, o.gpart, cs)
+                              : launch_accum_adj(L, C.ring, ns, k_last, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c,
+                                                 o.vbar, o.gpart, cs);
             };
             const int kind = o.hist ? TPX_KERNEL_ACCUM_FULL : TPX_KERNEL_ACCUM_ADJ;
             if (ovl) {
@@ -848,12 +918,15 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
             } else {
                 TPX_HIP(prof(kind, C.stream, contract));
             }
-            b.s_hi = k - 1;
+            b.s_hi = k_last - 1;
             ++b.blk;
         }
     }
     if (b.k < 1 && !b.finished) {
-        if (o.q_adj) TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(C.ring, L, ns, 0), 0, b.smp, C.stream); }));
+        for (; o.q_adj && b.next_row >= 0; --b.next_row) {
+            const int row = b.next_row;
+            TPX_HIP(prof(KIND_OTHER, C.stream, [&] { return launch_sample_only(L, slot_ptr(C.ring, L, ns, row), row, b.smp, C.stream); }));
+        }
         if (accum && C.plan.overlap) {
             tpx_status st = overlap_join(C, b.blk);
             if (st != TPX_OK) return st;

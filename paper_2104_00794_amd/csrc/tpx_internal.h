@@ -18,14 +18,17 @@ namespace tpx {
 //                  multiple of 32 floats;
 //   yg in [0, G1): 3D only, R ghost planes on each side (2D: G1 = 1);
 //   zg in [0, G2): R ghost rows on each side.
-// Ghost cells are zero forever (Dirichlet condition outside the padded box)
-// so the stencil kernels need no bounds tests on neighbour reads.
+// The field is zero outside the padded box (Dirichlet condition).  Kernels
+// read only nodes of the padded box and substitute zero elsewhere, so ghost
+// cells never need clearing.
 // ---------------------------------------------------------------------------
 constexpr int XO = 32;
 
-// 2D step kernel tile: 64 (x) by 32 (z) outputs, 256 threads.
-constexpr int T2X = 64;
+// 2D step kernel tile: T2Z rows by 64 - 2R columns of outputs, 256 threads.
+// One wave spans the tile's columns plus an R-wide halo on each side: the
+// region on which the first of two fused steps is computed.
 constexpr int T2Z = 32;
+__host__ __device__ constexpr int t2x(int R) { return 64 - 2 * R; }
 // 3D step kernel tile: 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
 constexpr int T3Y = 8;
@@ -48,6 +51,10 @@ struct Layout {
     int tile[3];
     int64_t ntiles[3];
     int64_t tiles_per_shot;
+    // injection map of one tile: extents and origin relative to the tile's
+    // first node (2D: 64 x (T2Z + 2R) nodes from (-R, -R); 3D: the tile)
+    int map[3];
+    int map_org[3];
 
     // offset (floats, within one shot) of padded node (ix, iy, iz)
     __host__ __device__ inline int64_t pad_off(int64_t ix, int64_t iy, int64_t iz) const {
@@ -64,8 +71,9 @@ struct Physics {
 
 // Point-source injection into one step.  A segment is the ordered run of
 // (source index, weight) entries of one target node.  tile_dense[tile] is -1
-// for a tile without sources, else the index of its dense map: dense[map *
-// nodes_per_tile + local node] = segment of that node or -1.
+// for a tile whose map holds no source node, else the index of its dense map:
+// dense[map * map_nodes + local node] = segment of that node or -1.  A node
+// inside several tiles' maps has the same segment contents in each.
 struct InjectTables {
     const int32_t *tile_dense; // [S * tiles_per_shot]
     const int32_t *dense;      // [maps][nodes per tile]
@@ -93,14 +101,22 @@ struct SampleTables {
     float scale;
 };
 
+// One launch advances one or two leapfrog steps.  Time runs forward (u^k ->
+// u^{k+1}) or backward (adjoint: lambda^k -> lambda^{k-1}); "next" is the
+// level after `cur` in the direction of the loop.
 struct StepArgs {
     const float *cur;   // u^k (slot base, shot 0)
     const float *prev;  // u^{k-1}
     float *next;        // u^{k+1}
+    float *next2;       // u^{k+2} (two-step launches only)
     const float *beta;  // dt^2 / m_pad, one shot-sized field
-    int k;              // time index of `cur` (selects amplitudes and sample rows)
+    int nstep;          // 1 or 2 (two steps: 2D only)
+    int k;              // time index of `cur`: amplitudes of the first step, sample row of `cur`
+    int k2;             // amplitude index of the second step
+    int kp;             // time index of `prev` (its sample row)
     int inject;         // 0/1
-    int do_sample;      // 0/1
+    int do_sample;      // 0/1: sample `cur` at row k
+    int sample_prev;    // 0/1: sample `prev` at row kp
     InjectTables inj;
     Amplitude amp;
     SampleTables smp;

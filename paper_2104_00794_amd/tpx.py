@@ -407,7 +407,7 @@ class Job:
             pass
 
 
-KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL = range(4)
+KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL, KERNEL_STEP2 = range(5)
 OPT_OVERLAP_CONTRACTIONS = 1
 
 
