@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_2104_00794_amd import profiling  # noqa: E402  (reads measured traffic records only)
+
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 
 
@@ -169,8 +171,10 @@ def main():
             bytes_per_launch = S * npad * (16.0 if two else 12.0) + npad * 4.0
             achieved = bytes_per_launch / (st["avg_us"] * 1e-6) / 1e9
             R = wl.order // 2
+            tag = ("k_step2d_x2" if two else "k_step2d") if wl.ndim == 2 else "k_step3d"
+            traffic = profiling.read_traffic(wl.name, tag)   # None unless measured with this kernel source
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "kernel": ("k_step2d<R=%d,NSTEP=%d>" % (R, 2 if two else 1)) if wl.ndim == 2 else
                         "k_step3d<R=%d>" % R,
                         "bytes_per_launch": bytes_per_launch, "avg_launch_us": st["avg_us"]}

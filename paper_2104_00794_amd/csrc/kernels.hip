@@ -305,10 +305,16 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
     constexpr int TX = t2x(R), TZ = T2Z;
     __shared__ float U[TZ + 4 * R][64 + 2 * R];
     __shared__ float V[NSTEP == 2 ? TZ + 2 * R : 1][64];
-    const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2];
-    const int lid = xcd_logical_block(ntx * ntz * L.S);
+    const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2], nsp = ntx * ntz;
+    const int lid = xcd_logical_block(nsp * L.S);
     if (lid < 0) return;
-    const int bx = lid % ntx, bz = (lid / ntx) % ntz, shot = lid / (ntx * ntz);
+    // Shots are split into eight equal groups when they divide evenly, one
+    // group per XCD; inside a group the shots of one spatial tile are adjacent,
+    // so the tile's beta is fetched once into that XCD's L2 for all of them.
+    const int sg = L.S % 8 == 0 ? L.S / 8 : 1;
+    const int grp = lid / (nsp * sg), rem = lid - grp * (nsp * sg);
+    const int sp = rem / sg, shot = grp * sg + (rem - sp * sg);
+    const int bx = sp % ntx, bz = sp / ntx;
     const int x0 = bx * TX, z0 = bz * TZ, nb = L.nb;
     const bool fast = x0 - 2 * R >= 0 && z0 - 2 * R >= 0 && x0 + TX + 2 * R <= (int)L.P[0] &&
                       z0 + TZ + 2 * R <= (int)L.P[2] && x0 - R >= nb && z0 - R >= nb &&
@@ -400,8 +406,12 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
         const bool zr = z + R < P2;
         qa[2 * R] = (ca && zr) ? cur[zo + R * PL + cola] : 0.0f;
         qb[2 * R] = (cb && zr) ? cur[zo + R * PL + colb] : 0.0f;
-        const float pa = oa ? prev[zo + cola] : 0.0f, pb = ob ? prev[zo + colb] : 0.0f;
-        const float ba = oa ? beta[zo + cola] : 0.0f, bb = ob ? beta[zo + colb] : 0.0f;
+        // u^{k-1} and beta are read once and u^{k+1} written once per launch:
+        // streamed past the caches (measured: less traffic than cached access)
+        const float pa = oa ? __builtin_nontemporal_load(prev + zo + cola) : 0.0f;
+        const float pb = ob ? __builtin_nontemporal_load(prev + zo + colb) : 0.0f;
+        const float ba = oa ? __builtin_nontemporal_load(beta + zo + cola) : 0.0f;
+        const float bb = ob ? __builtin_nontemporal_load(beta + zo + colb) : 0.0f;
 
         float(*pt)[W] = plane_t[lz & 1];
         pt[ly][lx] = h[0];
@@ -440,8 +450,8 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
                                   lapb);
         }
         const float hz = layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb);
-        if (oa) next[zo + cola] = leapfrog(qa[R], pa, ba, lapa, sa, ph.hd_max * (hxy_a + hz));
-        if (ob) next[zo + colb] = leapfrog(qb[R], pb, bb, lapb, sbv, ph.hd_max * (hxy_b + hz));
+        if (oa) __builtin_nontemporal_store(leapfrog(qa[R], pa, ba, lapa, sa, ph.hd_max * (hxy_a + hz)), next + zo + cola);
+        if (ob) __builtin_nontemporal_store(leapfrog(qb[R], pb, bb, lapb, sbv, ph.hd_max * (hxy_b + hz)), next + zo + colb);
 #pragma unroll
         for (int i = 0; i < 2 * R; ++i) {
             qa[i] = qa[i + 1];

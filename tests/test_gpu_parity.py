@@ -335,3 +335,23 @@ def test_overlapped_contractions_are_bitwise_identical():
     assert np.array_equal(to_np(a), to_np(b)) and float(Ja.item()) == float(Jb.item())
     assert np.array_equal(to_np(full0), to_np(full1))
     assert np.array_equal(to_np(job.g), to_np(a))
+
+
+def test_one_and_two_step_launches_are_bitwise_identical():
+    import torch
+
+    # A job advanced one time step per call runs only one-step launches; the
+    # gradient call fuses steps in pairs (odd nt leaves a single step at the
+    # end of each pass).  Rounding is pinned, so both give the same bits.
+    print("[case] one-step vs two-step launches, 2D", flush=True)
+    c = Case(small_2d(nz=45, nx=130, nt=151, nshots=3, nrec=17))
+    dobs = c.dobs_oracle()
+    probe = tpx.Probe(r=8, seed=5, block=16)
+    g2, J2 = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    job = tpx.Job(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    while not job.advance(1):
+        pass
+    torch.cuda.synchronize()
+    assert torch.equal(job.g, g2) and torch.equal(job.J, J2)
+    g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=8, seed=5)
+    assert rel_l2(to_np(g2), g_o) <= 1e-4
