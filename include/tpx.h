@@ -113,6 +113,13 @@ typedef struct {
     int32_t block;     /* time steps per probe contraction; 0 = library default */
     int32_t keep_vbar; /* 0: fold the adjoint accumulation into the gradient
                           (no vbar array); 1: accumulate vbar, then image */
+    int32_t dtt_side;  /* which pass probes the second time difference:
+                          0: ubar_j = sum_s Z[s,j] u^s (s = 1..nt-1) and
+                             vbar_j = sum_s Z[s,j] (lam^{s-1} - 2 lam^s + lam^{s+1});
+                          1 (Algorithm 1 as printed): ubar_j = sum_k Z[k,j]
+                             (u^{k+1} - 2 u^k + u^{k-1}) and vbar_j = sum_k Z[k,j]
+                             lam^k (k = 0..nt-2).  Both are unbiased estimators of
+                             the gradient of Eq. 3 and equal it for Z = I. */
 } tpx_probe;
 
 /* Call identifiers for tpx_workspace_bytes. */

@@ -688,11 +688,11 @@ __global__ __launch_bounds__(256) void k_accum_fwd(const Layout L, const float *
     for (int j = 0; j < RC; ++j) ub[(int64_t)j * L.nphys] += acc[j];
 }
 
-// One buffered step of the adjoint contraction: w = lam^{s-1} - 2 lam^s + lam^{s+1}.
-template <int RC, int FOLD>
+// One buffered step: w = f^{s-1} - 2 f^s + f^{s+1} (SD) or w = f^s (lp holds f^s).
+template <int RC, int FOLD, int SD>
 __device__ __forceinline__ void adj_step(float &lm, float &l0, float lp, const float *zr, const float *u, float *acc,
                                          float &fsum) {
-    const float w = (lm - 2.0f * l0) + lp;
+    const float w = SD ? (lm - 2.0f * l0) + lp : lp;
     if (FOLD) {
         float t = 0.0f;
 #pragma unroll
@@ -706,9 +706,11 @@ __device__ __forceinline__ void adj_step(float &lm, float &l0, float lp, const f
     l0 = lp;
 }
 
-// Adjoint contraction of exactly RC probes j0..j0+RC-1: either
+// Contraction of exactly RC probes j0..j0+RC-1 over w^s, s = s_lo..s_hi: either
 // vbar_j += sum_s Z[s,j] w^s, or (FOLD) gpart -= c sum_s w^s sum_j Z[s,j] ubar_j.
-template <int RC, int FOLD>
+// SD = 1: w^s = f^{s-1} - 2 f^s + f^{s+1} (second time difference of the
+// buffered field f); SD = 0: w^s = f^s.
+template <int RC, int FOLD, int SD>
 __global__ __launch_bounds__(256) void k_accum_adj(const Layout L, const float *__restrict__ ring, int nslots,
                                                    int s_lo, int s_hi, const float *__restrict__ Z, int nt, int r,
                                                    int j0, const float *__restrict__ ubar, float c,
@@ -730,20 +732,22 @@ __global__ __launch_bounds__(256) void k_accum_adj(const Layout L, const float *
 #pragma unroll
         for (int j = 0; j < RC; ++j) u[j] = ub[(int64_t)j * L.nphys];
     }
-    float lm = ring_load(&base[(int64_t)((s_lo - 1) % nslots) * L.slot_floats]);
-    float l0 = ring_load(&base[(int64_t)(s_lo % nslots) * L.slot_floats]);
+    // SD: (lm, l0) hold f^{s-1}, f^s and the loads fetch f^{s+1}; otherwise the loads fetch f^s
+    const int ahead = SD ? 1 : 0;
+    float lm = SD ? ring_load(&base[(int64_t)(((s_lo - 1) % nslots + nslots) % nslots) * L.slot_floats]) : 0.0f;
+    float l0 = SD ? ring_load(&base[(int64_t)(s_lo % nslots) * L.slot_floats]) : 0.0f;
     float fsum = 0.0f;
     int s = s_lo;
     for (; s + kAccUnroll - 1 <= s_hi; s += kAccUnroll) {
         float lp[kAccUnroll];
 #pragma unroll
-        for (int q = 0; q < kAccUnroll; ++q) lp[q] = ring_load(&base[(int64_t)((s + q + 1) % nslots) * L.slot_floats]);
+        for (int q = 0; q < kAccUnroll; ++q) lp[q] = ring_load(&base[(int64_t)((s + q + ahead) % nslots) * L.slot_floats]);
 #pragma unroll
-        for (int q = 0; q < kAccUnroll; ++q) adj_step<RC, FOLD>(lm, l0, lp[q], Zs + (int64_t)(s + q) * r, u, acc, fsum);
+        for (int q = 0; q < kAccUnroll; ++q) adj_step<RC, FOLD, SD>(lm, l0, lp[q], Zs + (int64_t)(s + q) * r, u, acc, fsum);
     }
     for (; s <= s_hi; ++s)
-        adj_step<RC, FOLD>(lm, l0, ring_load(&base[(int64_t)((s + 1) % nslots) * L.slot_floats]),
-                           Zs + (int64_t)s * r, u, acc, fsum);
+        adj_step<RC, FOLD, SD>(lm, l0, ring_load(&base[(int64_t)((s + ahead) % nslots) * L.slot_floats]),
+                               Zs + (int64_t)s * r, u, acc, fsum);
     if (FOLD) {
         gpart[(int64_t)shot * L.nphys + pi.p] -= c * fsum;
     } else {
@@ -823,13 +827,13 @@ hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int 
     return hipGetLastError();
 }
 
-template <int FOLD>
+template <int FOLD, int SD>
 static void launch_adj_chunks(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots, int s_lo,
                               int s_hi, const float *Z, int nt, int r, const float *ubar, float c, float *vbar,
                               float *gpart) {
     for (int j0 = 0; j0 < r;) {
         const int rc = chunk_of(r - j0);
-#define TPX_ADJ(RC) hipLaunchKernelGGL((k_accum_adj<RC, FOLD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar, c, vbar, gpart)
+#define TPX_ADJ(RC) hipLaunchKernelGGL((k_accum_adj<RC, FOLD, SD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar, c, vbar, gpart)
         switch (rc) {
         case 64: TPX_ADJ(64); break;
         case 32: TPX_ADJ(32); break;
@@ -845,12 +849,14 @@ static void launch_adj_chunks(const Layout &L, dim3 g, hipStream_t stream, const
 }
 
 hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,
-                            int nt, int r, int fold, const float *ubar, float c, float *vbar, float *gpart,
+                            int nt, int r, int fold, int sd, const float *ubar, float c, float *vbar, float *gpart,
                             hipStream_t stream) {
     if (s_hi < s_lo) return hipSuccess;
     const dim3 g = point_grid(L);
-    if (fold) launch_adj_chunks<1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
-    else launch_adj_chunks<0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    if (fold && sd) launch_adj_chunks<1, 1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    else if (fold) launch_adj_chunks<1, 0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    else if (sd) launch_adj_chunks<0, 1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    else launch_adj_chunks<0, 0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
     return hipGetLastError();
 }
 

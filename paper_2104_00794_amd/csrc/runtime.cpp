@@ -454,6 +454,7 @@ tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     if (pr->kind == TPX_PROBE_IDENTITY && pr->r != P.nt) return fail(TPX_E_INVAL, "identity probes need r == nt");
     if (pr->kind == TPX_PROBE_EXPLICIT && !pr->Z) return fail(TPX_E_INVAL, "explicit probes need Z");
     if (pr->block < 0) return fail(TPX_E_INVAL, "block must be >= 0");
+    if (pr->dtt_side != 0 && pr->dtt_side != 1) return fail(TPX_E_INVAL, "dtt_side must be 0 or 1");
     return TPX_OK;
 }
 
@@ -690,6 +691,7 @@ struct FwdLoop {
     const float *Z = nullptr;
     int r = 0;
     float *ubar = nullptr;
+    int dtt = 0;   // 1: ubar accumulates second time differences of u (Algorithm 1 side)
     int k = 0;
     int s_lo = 1;
     int next_row = 0;  // first trace row not sampled yet
@@ -703,7 +705,7 @@ struct FwdLoop {
 bool two_steps_allowed(const Ctx &C) { return C.P.L.ndim == 2 && !C.plan.overlap; }
 
 tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
-                     float *ubar) {
+                     float *ubar, int dtt = 0) {
     const Layout &L = C.P.L;
     const int nt = C.P.nt;
     f.buf = hist ? hist : C.ring;
@@ -711,6 +713,7 @@ tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *
     f.Z = Z;
     f.r = r;
     f.ubar = ubar;
+    f.dtt = dtt;
     f.k = 0;
     f.s_lo = 1;
     f.next_row = 0;
@@ -719,6 +722,8 @@ tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *
     // u^{-1} = u^0 = 0: the first step reads slot 0 as both levels.  Other
     // slots are written before they are read, and ghost cells are never read.
     TPX_HIP(fill_zero_p(slot_ptr(f.buf, L, f.ns, 0), (size_t)L.slot_floats * 4, C.stream));
+    // the second difference at k = 0 reads u^{-1} = 0 from the slot before slot 0
+    if (Z && dtt) TPX_HIP(fill_zero_p(slot_ptr(f.buf, L, f.ns, -1), (size_t)L.slot_floats * 4, C.stream));
     if (ubar) TPX_HIP(fill_zero_p(ubar, align_up((size_t)L.S * r * L.nphys * 4), C.stream));
     StepArgs &a = f.a;
     memset(&a, 0, sizeof a);
@@ -774,14 +779,18 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
         if (f.Z && (s_last - f.s_lo + 1 == C.plan.block || s_last == nt - 1)) {
             const int s_lo = f.s_lo;
             const int s_hi = s_last;
+            // levels s_lo..s_hi are new: contract them (dtt 0), or the second
+            // differences centred at k = s_lo-1..s_hi-1, which they complete (dtt 1)
+            auto contract = [&](hipStream_t cs) {
+                return f.dtt ? launch_accum_adj(L, f.buf, f.ns, s_lo - 1, s_hi - 1, f.Z, nt, f.r, 0, 1, nullptr, 1.0f,
+                                                f.ubar, nullptr, cs)
+                             : launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, cs);
+            };
             if (ovl) {
-                tpx_status st = overlap_launch(C, f.blk, TPX_KERNEL_ACCUM_FWD, [&] {
-                    return launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, C.aux);
-                });
+                tpx_status st = overlap_launch(C, f.blk, TPX_KERNEL_ACCUM_FWD, [&] { return contract(C.aux); });
                 if (st != TPX_OK) return st;
             } else {
-                TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream,
-                             [&] { return launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, C.stream); }));
+                TPX_HIP(prof(TPX_KERNEL_ACCUM_FWD, C.stream, [&] { return contract(C.stream); }));
             }
             f.s_lo = s_hi + 1;
             ++f.blk;
@@ -802,9 +811,10 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
     return TPX_OK;
 }
 
-tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, const float *Z, int r, float *ubar) {
+tpx_status run_forward(Ctx &C, const float *wavelet, float *d, float *hist, const float *Z, int r, float *ubar,
+                       int dtt = 0) {
     FwdLoop f;
-    tpx_status st = fwd_begin(C, f, wavelet, d, hist, Z, r, ubar);
+    tpx_status st = fwd_begin(C, f, wavelet, d, hist, Z, r, ubar, dtt);
     if (st != TPX_OK) return st;
     return fwd_advance(C, f, INT64_MAX, nullptr);
 }
@@ -817,6 +827,7 @@ struct AdjOut {
     const float *Z = nullptr;
     int r = 0;
     int fold = 1;
+    int dtt = 0;   // 1: contract lam^k itself (Algorithm 1 side), else its second difference
     const float *ubar = nullptr;
     float c = 1.0f;
     float *vbar = nullptr;
@@ -906,10 +917,14 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
         if (accum && (b.s_hi - k_last + 1 == C.plan.block || k_last == 1)) {
             const int s_hi = b.s_hi;
             hipStream_t cs = ovl ? C.aux : C.stream;
+            // dtt 0: w^s for s = k_last..s_hi; dtt 1: lam^k itself for k in the same
+            // range, lam^0 joining the last block and lam^{nt-1} = 0 left out
+            const int lo = o.dtt && k_last == 1 ? 0 : k_last;
+            const int hi = o.dtt ? std::min(s_hi, nt - 2) : s_hi;
             auto contract = [&] {
                 return o.hist ? launch_accum_full(L, o.hist, C.ring, ns, k_last, s_hi, o.gpart, cs)
-                              : launch_accum_adj(L, C.ring, ns, k_last, s_hi, o.Z, nt, o.r, o.fold, o.ubar, o.c,
-                                                 o.vbar, o.gpart, cs);
+                              : launch_accum_adj(L, C.ring, ns, lo, hi, o.Z, nt, o.r, o.fold, o.dtt ? 0 : 1, o.ubar,
+                                                 o.c, o.vbar, o.gpart, cs);
             };
             const int kind = o.hist ? TPX_KERNEL_ACCUM_FULL : TPX_KERNEL_ACCUM_ADJ;
             if (ovl) {
@@ -1010,7 +1025,7 @@ tpx_status job_init(GradJob &J, const tpx_grid *grid, const tpx_geom *geom, cons
     J.ubar = (float *)(J.C.ws + J.C.plan.ubar);
     J.Z = probe_matrix_dev(J.C, probe, &st);
     if (st != TPX_OK) return st;
-    st = fwd_begin(J.C, J.f, J.wavelet, J.d, nullptr, J.Z, probe->r, J.ubar);
+    st = fwd_begin(J.C, J.f, J.wavelet, J.d, nullptr, J.Z, probe->r, J.ubar, probe->dtt_side);
     if (st != TPX_OK) return st;
     J.phase = 0;
     J.done_steps = 0;
@@ -1037,6 +1052,7 @@ tpx_status job_advance(GradJob &J, int64_t max_steps) {
             o.Z = J.Z;
             o.r = J.probe.r;
             o.fold = J.probe.keep_vbar ? 0 : 1;
+            o.dtt = J.probe.dtt_side;
             o.ubar = J.ubar;
             o.c = probe_scale(&J.probe);
             o.vbar = J.probe.keep_vbar ? (float *)(J.C.ws + J.C.plan.vbar) : nullptr;
@@ -1225,7 +1241,7 @@ tpx_status tpx_forward_probed(const tpx_grid *grid, const tpx_geom *geom, const 
         if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
         const float *Z = probe_matrix_dev(C, probe, &st);
         if (st != TPX_OK) return st;
-        return run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, (float *)state);
+        return run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, (float *)state, probe->dtt_side);
     });
 }
 
@@ -1246,6 +1262,7 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
         o.Z = Z;
         o.r = probe->r;
         o.fold = probe->keep_vbar ? 0 : 1;
+        o.dtt = probe->dtt_side;
         o.ubar = (const float *)state;
         o.c = probe_scale(probe);
         o.vbar = probe->keep_vbar ? (float *)(C.ws + C.plan.vbar) : nullptr;

@@ -138,12 +138,13 @@ hipError_t launch_probe_copy(const float *Zsrc, int64_t n, float *Zdst, hipStrea
 // ubar[shot][j][p] += sum_{s=s_lo}^{s_hi} Z[shot][s][j] * u^s[p]  (physical p)
 hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi,
                             const float *Z, int nt, int r, float *ubar, hipStream_t stream);
-// w^s = lam^{s-1} - 2 lam^s + lam^{s+1} from the ring; either
+// w^s from the buffered field f: f^{s-1} - 2 f^s + f^{s+1} (sd == 1) or f^s
+// (sd == 0), s = s_lo..s_hi; either
 //   vbar[shot][j][p] += sum_s Z[shot][s][j] w^s[p]          (fold == 0), or
 //   gpart[shot][p]   += -c sum_s w^s[p] sum_j Z[s][j] ubar_j[p]   (fold == 1)
 hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi,
-                            const float *Z, int nt, int r, int fold, const float *ubar, float c, float *vbar,
-                            float *gpart, hipStream_t stream);
+                            const float *Z, int nt, int r, int fold, int sd, const float *ubar, float c,
+                            float *vbar, float *gpart, hipStream_t stream);
 // gpart[shot][p] += - sum_s u^s[p] w^s[p], u^s from the full history (slot s)
 hipError_t launch_accum_full(const Layout &L, const float *hist, const float *ring, int nslots, int s_lo,
                              int s_hi, float *gpart, hipStream_t stream);

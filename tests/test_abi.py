@@ -87,3 +87,12 @@ def test_full_history_of_3d_config_exceeds_one_gpu():
     probed = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=32))
     assert full > 288e9
     assert probed < 0.25 * 288e9
+
+
+def test_probe_side_validated():
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]])
+    ok = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4, dtt_side=1))
+    assert ok == tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4))
+    with pytest.raises(tpx.TpxError):
+        tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4, dtt_side=2))
