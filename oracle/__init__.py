@@ -14,6 +14,7 @@ Paper sections followed (Louboutin & Herrmann, arXiv 2104.00794):
   * exact gradient sum_t  u_tt[t] v[t] ......... Methodology, Eq. (3)
   * probed gradient (1/r) tr((Q^T u_tt)(v^T Q)) . Methodology, Eq. (4), Algorithm 1
   * probes: Rademacher / Gaussian ............. Randomized trace estimation, Eq. (1)
+  * probes from the data's range, Q = qr(D D^T Z) . Choice of the probing matrix Q, Eq. (6)
 
 Parity status: all functions are pinned by ``tests/test_oracle_*.py`` against
 closed forms, invariants, brute force and NumPy's Philox known-answer vectors.
@@ -244,6 +245,22 @@ def gradient_probed(grid: Grid, m, src_pos, rec_pos, wavelet, d_obs, kind="radem
     if return_traces:
         return g, float(J[0]), dout
     return g, float(J[0])
+
+
+def range_finder_probes(d_obs, r: int, seed: int) -> np.ndarray:
+    """Probing matrices that capture the range of the data's time covariance
+    (Choice of the probing matrix Q, Eq. 6): per shot, the observed traces form
+    D (nt x nrec), A = D D^T, and Q is the orthonormal factor of the reduced QR
+    of A Z, with Z that shot's Rademacher probing matrix (same seed and counter
+    as ``probe_matrix``).  Returns Q as [S][nt][r]; it is used with c = 1."""
+    D = np.asarray(d_obs, dtype=np.float64)
+    S, nt, nrec = D.shape
+    Q = np.empty((S, nt, r))
+    for s in range(S):
+        Z = probe_matrix("rademacher", r, seed, nt, s)
+        Y = D[s] @ (D[s].T @ Z)   # A Z, with A applied in factored form
+        Q[s] = np.linalg.qr(Y, mode="reduced")[0]
+    return Q
 
 
 def probe_matrix(kind, r: int, seed: int, nt: int, shot: int) -> np.ndarray:

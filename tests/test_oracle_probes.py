@@ -100,3 +100,48 @@ def test_shots_and_seeds_give_independent_streams():
     c = oracle.probe_matrix("rademacher", 16, 2, 64, 0)
     assert not np.array_equal(a, b) and not np.array_equal(a, c)
     assert abs(np.mean(a * b)) < 0.15 and abs(np.mean(a * c)) < 0.15
+
+
+# --------------------------------------------------------------------------- #
+# probes from the range of the data covariance (Eq. 6)
+# --------------------------------------------------------------------------- #
+
+def _numpy_rademacher(seed, nt, r, shot):
+    Z = np.empty((nt, r))
+    for t in range(nt):
+        for j in range(r):
+            Z[t, j] = 1.0 - 2.0 * (int(_numpy_block(seed, t, j, shot)[0]) >> 63)
+    return Z
+
+
+def test_range_finder_probes_are_orthonormal_and_span_AZ():
+    rng = np.random.default_rng(3)
+    S, nt, nrec, r, seed = 2, 90, 25, 7, 41
+    D = rng.standard_normal((S, nt, nrec)).astype(np.float32)
+    Q = oracle.range_finder_probes(D, r, seed)
+    assert Q.shape == (S, nt, r)
+    for s in range(S):
+        assert np.abs(Q[s].T @ Q[s] - np.eye(r)).max() <= 1e-12
+        # A formed explicitly, Z from NumPy's own Philox stream of this shot
+        A = D[s].astype(np.float64) @ D[s].T.astype(np.float64)
+        Y = A @ _numpy_rademacher(seed, nt, r, s)
+        resid = Y - Q[s] @ (Q[s].T @ Y)
+        assert np.linalg.norm(resid) <= 1e-11 * np.linalg.norm(Y)
+    # another shot's Z spans a different space
+    Y0 = D[0].astype(np.float64) @ (D[0].T.astype(np.float64) @ _numpy_rademacher(seed, nt, r, 1))
+    assert np.linalg.norm(Y0 - Q[0] @ (Q[0].T @ Y0)) > 1e-3 * np.linalg.norm(Y0)
+
+
+def test_range_finder_recovers_the_trace_of_a_low_rank_covariance():
+    # rank(D D^T) = k <= r: A Z spans the whole range of A, so the probed trace
+    # tr(Q^T A Q) (c = 1) equals tr(A) = ||D||_F^2 exactly up to rounding,
+    # while r Rademacher probes (c = 1/r) do not
+    rng = np.random.default_rng(8)
+    nt, nrec, k, r = 120, 40, 3, 5
+    D = (rng.standard_normal((nt, k)) @ rng.standard_normal((k, nrec)))[None]
+    Q = oracle.range_finder_probes(D, r, seed=9)[0]
+    A = D[0] @ D[0].T
+    tr = np.sum(D[0] ** 2)
+    assert abs(np.trace(Q.T @ A @ Q) - tr) <= 1e-10 * tr
+    Z = oracle.probe_matrix("rademacher", r, 9, nt, 0)
+    assert abs(np.trace(Z.T @ A @ Z) / r - tr) > 1e-3 * tr
