@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c1_layered_2d_16shots")
     ap.add_argument("--r", type=int, default=None, help="probes (default: the workload's)")
-    ap.add_argument("--probe", default=None, help="rademacher | gauss_b64")
+    ap.add_argument("--probe", default=None, help="rademacher | gauss_b64 | range_finder")
     ap.add_argument("--block", type=int, default=0, help="time steps per probe contraction (0 = default)")
     ap.add_argument("--keep-vbar", action="store_true", help="accumulate vbar instead of folding it")
     ap.add_argument("--overlap", action="store_true",
@@ -185,7 +185,7 @@ def main():
         # about 10-30 s of oracle work: the full record of one 2D shot, or a
         # short window of the 3D record
         cpu = cpu_baseline(wl, r, kind, args.cpu_nt or (wl.nt if wl.ndim == 2 else 24),
-                           min(4, wl.nshots) if wl.ndim == 2 else 1)
+                           min(4, wl.nshots) if wl.ndim == 2 else 1, d_obs)
 
     out = {
         "metric": "GPts/s fwd+adj with r-probe accumulation (%HBM roofline); gradient p50/p99 latency",
@@ -263,7 +263,7 @@ def serving(args, dev):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, r, kind, nt_sample, shots):
+def cpu_baseline(wl, r, kind, nt_sample, shots, d_obs):
     """FP64 oracle on the first `shots` shots of the workload, first nt_sample time steps."""
     import oracle
     oracle.build(force=False)
@@ -271,10 +271,16 @@ def cpu_baseline(wl, r, kind, nt_sample, shots):
     mt, m0 = sample.models()
     og = oracle.Grid(sample.shape, h=sample.h, dt=sample.dt, nt=sample.nt, order=sample.order, nbl=sample.nbl,
                      damp_vmax=sample.vmax, damp_R=sample.damp_R)
-    dobs = np.zeros((sample.nshots, sample.nt, len(sample.rec)))
+    # the workload's observed traces, cut to the sample
+    dobs = d_obs[:shots, :nt_sample].double().cpu().numpy()
     t0 = time.perf_counter()
-    oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind=kind, r=r,
-                           seed=sample.probe_seed)
+    if kind == "range_finder":
+        Q = oracle.range_finder_probes(dobs, r, sample.probe_seed)
+        oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind="explicit",
+                               r=r, Z=Q, scale=1.0)
+    else:
+        oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind=kind, r=r,
+                               seed=sample.probe_seed)
     dt = time.perf_counter() - t0
     upd = sample.nshots * sample.n_pad * 2 * (sample.nt - 1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

@@ -98,7 +98,14 @@ typedef enum {
     TPX_PROBE_RADEMACHER = 0, /* random +-1 (Randomized trace estimation) */
     TPX_PROBE_GAUSS_B64 = 1,  /* "Gaussian": (popcount(w) - 32) / 4, unit variance */
     TPX_PROBE_IDENTITY = 2,   /* Z = I, requires r == nt: exact gradient */
-    TPX_PROBE_EXPLICIT = 3    /* caller-provided Z (e.g. an orthonormal basis) */
+    TPX_PROBE_EXPLICIT = 3,   /* caller-provided Z (e.g. an orthonormal basis) */
+    TPX_PROBE_RANGE_FINDER = 4 /* Q = qr(D_obs D_obs^T Z) per shot, Z Rademacher
+                                  (Choice of the probing matrix Q, Eq. 6):
+                                  orthonormal, c = 1.  Needs the observed data,
+                                  so gradient calls and jobs only (the split
+                                  forward/backward pair takes it as EXPLICIT
+                                  from tpx_range_finder_probes); 1 <= r <=
+                                  min(64, nrec, nt). */
 } tpx_probe_kind;
 
 /* Probing (Eq. 1, Eq. 4).  Random entries are Philox4x64-10 (Salmon et al.,
@@ -129,7 +136,8 @@ enum {
     TPX_CALL_GRADIENT_PROBED = 2,
     TPX_CALL_GRADIENT_FULL = 3,
     TPX_CALL_FORWARD_PROBED = 4,
-    TPX_CALL_BACKWARD_PROBED = 5
+    TPX_CALL_BACKWARD_PROBED = 5,
+    TPX_CALL_RANGE_FINDER = 6
 };
 
 /* Device workspace (bytes) that `call` needs for this problem; 0 on invalid
@@ -222,6 +230,18 @@ enum {
 };
 void tpx_profile_enable(int32_t on);
 tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches);
+
+/* Probes from the range of the data covariance (Choice of the probing
+ * matrix Q, Eq. 6): for every shot, D = d_obs[shot] as an nt x nrec matrix,
+ * Z = the shot's Rademacher probes (probe->seed), Q[shot] = the orthonormal
+ * factor of the reduced QR of D D^T Z, computed in FP64 and stored as float
+ * Q[S][nt][r] (device).  Use it as EXPLICIT probes with scale 1.  Only
+ * grid->nt, geom->nshots and geom->nrec are used of the problem; the
+ * workspace is tpx_workspace_bytes(TPX_CALL_RANGE_FINDER, ...).
+ * probe->kind must be TPX_PROBE_RANGE_FINDER; E_INVAL unless
+ * 1 <= r <= min(64, nrec, nt). */
+tpx_status tpx_range_finder_probes(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe,
+                                   const float *d_obs, float *Q, void *ws, size_t ws_bytes, void *stream);
 
 /* Probing matrix of one shot as the GPU generates it: Z[nt][r] (device). */
 tpx_status tpx_probe_matrix(const tpx_probe *probe, int32_t nt, int32_t shot, float *Z, void *stream);

@@ -968,4 +968,191 @@ hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Probes from the range of the data covariance (Choice of the probing matrix
+// Q, Eq. 6): per shot Q = qr(D D^T Z), D = observed traces as nt x nrec, Z the
+// shot's Rademacher probes.  FP64 throughout, fixed summation orders.
+// ---------------------------------------------------------------------------
+
+// W[s][i][j0 + c] = sum_t D[s][t][i] Z[s][t][j0 + c], c < RC: one thread per receiver.
+template <int RC>
+__global__ __launch_bounds__(256) void k_rf_dtz(int nt, int nrec, int r, int j0, const float *__restrict__ D,
+                                                const float *__restrict__ Z, double *__restrict__ W) {
+    const int s = blockIdx.y;
+    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (i >= nrec) return;
+    const float *Ds = D + (int64_t)s * nt * nrec + i;
+    const float *Zs = Z + (int64_t)s * nt * r + j0;
+    double acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        const double d = (double)Ds[(int64_t)t * nrec];
+        const float *zr = Zs + (int64_t)t * r;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] = fma(d, (double)zr[c], acc[c]);
+    }
+    double *w = W + ((int64_t)s * nrec + i) * r + j0;
+#pragma unroll
+    for (int c = 0; c < RC; ++c) w[c] = acc[c];
+}
+
+// Y[s][t][j0 + c] = sum_i D[s][t][i] W[s][i][j0 + c]: one wave per time
+// sample; lanes stride the receivers, then a fixed butterfly sums the lanes.
+template <int RC>
+__global__ __launch_bounds__(256) void k_rf_dw(int nt, int nrec, int r, int j0, const float *__restrict__ D,
+                                               const double *__restrict__ W, double *__restrict__ Y) {
+    const int s = blockIdx.y;
+    const int t = (int)blockIdx.x * 4 + ((int)threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= nt) return;   // whole waves leave together
+    const float *Dr = D + ((int64_t)s * nt + t) * nrec;
+    const double *Ws = W + (int64_t)s * nrec * r + j0;
+    double acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0.0;
+    for (int i = lane; i < nrec; i += 64) {
+        const double d = (double)Dr[i];
+        const double *wr = Ws + (int64_t)i * r;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) acc[c] = fma(d, wr[c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 64);
+    if (lane == 0) {
+        double *y = Y + ((int64_t)s * nt + t) * r + j0;
+#pragma unroll
+        for (int c = 0; c < RC; ++c) y[c] = acc[c];
+    }
+}
+
+// Householder QR of one shot's Y (nt x r, row-major) and the explicit
+// orthonormal factor, both in place (the unblocked LAPACK algorithms: the
+// reflector of column j is I - tau v v^T with v_j = 1, stored below the
+// diagonal; Q = H_0 ... H_{r-1} [I_r; 0] is then accumulated backwards).
+// Block = 1024 threads: 64 columns x 16 row groups for the column dot
+// products, summed over the row groups in a fixed order.  Q is written as
+// float [nt][r].
+__global__ __launch_bounds__(1024) void k_rf_qr(int nt, int r, double *__restrict__ Y, float *__restrict__ Q) {
+    const int s = blockIdx.x;
+    double *A = Y + (int64_t)s * nt * r;
+    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+    __shared__ double red[1024];
+    __shared__ double tau[64];
+    __shared__ double wv[64];
+    __shared__ double scale;
+
+    auto block_sum = [&](double v) {   // fixed-order tree over the 1024 threads
+        red[tid] = v;
+        __syncthreads();
+        for (int st = 512; st > 0; st >>= 1) {
+            if (tid < st) red[tid] += red[tid + st];
+            __syncthreads();
+        }
+        const double out = red[0];
+        __syncthreads();
+        return out;
+    };
+    // w_k = sum_{t >= j} v_t A[t][k] for k in (kmin, r), v_j = 1, v_t = A[t][j] below
+    auto column_dots = [&](int j, int kmin) {
+        double part = 0.0;
+        if (tx > kmin && tx < r)
+            for (int t = j + 1 + ty; t < nt; t += 16) part = fma(A[(int64_t)t * r + j], A[(int64_t)t * r + tx], part);
+        red[ty * 64 + tx] = part;
+        __syncthreads();
+        if (ty == 0 && tx > kmin && tx < r) {
+            double w = A[(int64_t)j * r + tx];
+            for (int g = 0; g < 16; ++g) w += red[g * 64 + tx];
+            wv[tx] = w;
+        }
+        __syncthreads();
+    };
+    // A[t][k] -= tau v_t w_k for t >= j, k in (kmin, r)
+    auto apply = [&](int j, int kmin, double tj) {
+        const int64_t n = (int64_t)(nt - j) * r;
+        for (int64_t idx = tid; idx < n; idx += 1024) {
+            const int t = j + (int)(idx / r), k = (int)(idx % r);
+            if (k > kmin) {
+                const double vt = t == j ? 1.0 : A[(int64_t)t * r + j];
+                A[(int64_t)t * r + k] -= tj * vt * wv[k];
+            }
+        }
+        __syncthreads();
+    };
+
+    for (int j = 0; j < r; ++j) {
+        double part = 0.0;
+        for (int t = j + 1 + tid; t < nt; t += 1024) {
+            const double x = A[(int64_t)t * r + j];
+            part = fma(x, x, part);
+        }
+        const double sigma = block_sum(part);
+        if (tid == 0) {
+            const double alpha = A[(int64_t)j * r + j];
+            if (sigma == 0.0) {          // already upper triangular here: H_j = I
+                tau[j] = 0.0;
+                scale = 0.0;
+            } else {
+                const double norm = sqrt(fma(alpha, alpha, sigma));
+                const double beta = alpha >= 0.0 ? -norm : norm;
+                tau[j] = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+                A[(int64_t)j * r + j] = beta;
+            }
+        }
+        __syncthreads();
+        const double tj = tau[j];
+        if (tj != 0.0) {
+            for (int t = j + 1 + tid; t < nt; t += 1024) A[(int64_t)t * r + j] *= scale;
+            __syncthreads();
+            column_dots(j, j);
+            apply(j, j, tj);
+        }
+    }
+    // explicit Q, accumulated from the last reflector to the first
+    for (int j = r - 1; j >= 0; --j) {
+        const double tj = tau[j];
+        if (j < r - 1 && tj != 0.0) {
+            column_dots(j, j);
+            apply(j, j, tj);
+        }
+        for (int t = tid; t < nt; t += 1024) {
+            double *a = &A[(int64_t)t * r + j];
+            if (t < j) *a = 0.0;
+            else if (t == j) *a = 1.0 - tj;
+            else *a = -tj * *a;
+        }
+        __syncthreads();
+    }
+    float *Qs = Q + (int64_t)s * nt * r;
+    for (int64_t idx = tid; idx < (int64_t)nt * r; idx += 1024) Qs[idx] = (float)A[idx];
+}
+
+hipError_t launch_range_finder(int S, int nt, int nrec, int r, const float *d_obs, float *Z, double *W, double *Y,
+                               hipStream_t stream) {
+    if (S < 1 || r < 1 || r > 64 || nrec < 1 || nt < r) return hipErrorInvalidValue;
+    const dim3 g1((unsigned)((nrec + 255) / 256), (unsigned)S), g2((unsigned)((nt + 3) / 4), (unsigned)S);
+    for (int j0 = 0; j0 < r;) {
+        int q = 16;
+        while (q > r - j0) q >>= 1;   // power-of-two chunks of the probe columns
+#define TPX_RF(RC)                                                                                           \
+    hipLaunchKernelGGL(k_rf_dtz<RC>, g1, dim3(256), 0, stream, nt, nrec, r, j0, d_obs, (const float *)Z, W); \
+    hipLaunchKernelGGL(k_rf_dw<RC>, g2, dim3(256), 0, stream, nt, nrec, r, j0, d_obs, (const double *)W, Y)
+        switch (q) {
+        case 16: TPX_RF(16); break;
+        case 8: TPX_RF(8); break;
+        case 4: TPX_RF(4); break;
+        case 2: TPX_RF(2); break;
+        default: TPX_RF(1); break;
+        }
+#undef TPX_RF
+        j0 += q;
+    }
+    // Z is read by the products above before the factorisation overwrites it with Q
+    hipLaunchKernelGGL(k_rf_qr, dim3((unsigned)S), dim3(1024), 0, stream, nt, r, Y, Z);
+    return hipGetLastError();
+}
+
 }  // namespace tpx

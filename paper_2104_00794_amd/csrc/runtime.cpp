@@ -440,17 +440,19 @@ int default_block(const Layout &L, int nt, bool overlap) {
 }
 
 struct Plan {
-    size_t flags, parts, J, beta, ring, hist, Z, ubar, vbar, gpart, res, d, tables, total;
+    size_t flags, parts, J, beta, ring, hist, Z, rfW, rfY, ubar, vbar, gpart, res, d, tables, total;
     int nslots, block;
     bool overlap;
 };
 
-enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED };
+enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED, M_RANGE_FINDER };
 
 tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     if (!pr) return fail(TPX_E_INVAL, "probe must not be NULL for probed calls");
     if (pr->r < 1) return fail(TPX_E_INVAL, "r must be >= 1");
-    if (pr->kind < 0 || pr->kind > 3) return fail(TPX_E_INVAL, "unknown probe kind");
+    if (pr->kind < 0 || pr->kind > 4) return fail(TPX_E_INVAL, "unknown probe kind");
+    if (pr->kind == TPX_PROBE_RANGE_FINDER && (pr->r > 64 || pr->r > P.nrec || pr->r > P.nt))
+        return fail(TPX_E_INVAL, "range-finder probes need r <= min(64, nrec, nt)");
     if (pr->kind == TPX_PROBE_IDENTITY && pr->r != P.nt) return fail(TPX_E_INVAL, "identity probes need r == nt");
     if (pr->kind == TPX_PROBE_EXPLICIT && !pr->Z) return fail(TPX_E_INVAL, "explicit probes need Z");
     if (pr->block < 0) return fail(TPX_E_INVAL, "block must be >= 0");
@@ -462,6 +464,12 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     const Layout &L = P.L;
     Plan p;
     memset(&p, 0, sizeof p);
+    if (mode == M_RANGE_FINDER) {   // FP64 scratch of the range finder only
+        p.rfW = 0;
+        p.rfY = align_up((size_t)L.S * P.nrec * pr->r * 8);
+        p.total = p.rfY + align_up((size_t)L.S * P.nt * pr->r * 8);
+        return p;
+    }
     const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
     const int r = probed ? pr->r : 0;
     p.overlap = g_overlap.load() != 0 && mode != M_FORWARD && mode != M_ADJOINT;
@@ -487,6 +495,10 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     p.ring = take(slot * p.nslots);
     if (mode == M_GRAD_FULL) p.hist = take(slot * (size_t)P.nt);
     if (probed && pr->kind != TPX_PROBE_EXPLICIT) p.Z = take((size_t)L.S * P.nt * r * 4);
+    if (probed && pr->kind == TPX_PROBE_RANGE_FINDER) {
+        p.rfW = take((size_t)L.S * P.nrec * pr->r * 8);
+        p.rfY = take((size_t)L.S * P.nt * pr->r * 8);
+    }
     if (mode == M_GRAD_PROBED) p.ubar = take((size_t)L.S * r * L.nphys * 4);
     const bool keep_v = probed && pr->keep_vbar;
     if ((mode == M_GRAD_PROBED || mode == M_BWD_PROBED) && keep_v) p.vbar = take((size_t)L.S * r * L.nphys * 4);
@@ -959,17 +971,30 @@ tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
     return adj_advance(C, b, INT64_MAX, nullptr);
 }
 
-const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, tpx_status *st) {
+// Probes of the call on the device: the caller's (EXPLICIT), generated from
+// the counter hash, or (RANGE_FINDER) the QR factor of D_obs D_obs^T Z.
+const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, const float *d_obs, tpx_status *st) {
     *st = TPX_OK;
     if (pr->kind == TPX_PROBE_EXPLICIT) return pr->Z;
     float *Z = (float *)(C.ws + C.plan.Z);
-    hipError_t e = prof(KIND_OTHER, C.stream, [&] { return launch_probe_gen(pr->kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream); });
+    const bool rf = pr->kind == TPX_PROBE_RANGE_FINDER;
+    if (rf && !d_obs) {
+        *st = fail(TPX_E_INVAL, "range-finder probes need the observed data");
+        return nullptr;
+    }
+    const int kind = rf ? TPX_PROBE_RADEMACHER : pr->kind;
+    hipError_t e = prof(KIND_OTHER, C.stream, [&] { return launch_probe_gen(kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream); });
+    if (e == hipSuccess && rf)
+        e = prof(KIND_OTHER, C.stream, [&] {
+            return launch_range_finder(C.P.L.S, C.P.nt, C.P.nrec, pr->r, d_obs, Z, (double *)(C.ws + C.plan.rfW),
+                                       (double *)(C.ws + C.plan.rfY), C.stream);
+        });
     if (e != hipSuccess) *st = fail(TPX_E_DEVICE, std::string("probe generation: ") + hipGetErrorString(e));
     return Z;
 }
 
 float probe_scale(const tpx_probe *pr) {
-    if (pr->kind == TPX_PROBE_IDENTITY) return 1.0f;
+    if (pr->kind == TPX_PROBE_IDENTITY || pr->kind == TPX_PROBE_RANGE_FINDER) return 1.0f;
     if (pr->kind == TPX_PROBE_EXPLICIT) return (float)pr->scale;
     return (float)(1.0 / pr->r);
 }
@@ -983,6 +1008,7 @@ Mode mode_of(int32_t call, bool *ok) {
     case TPX_CALL_GRADIENT_FULL: return M_GRAD_FULL;
     case TPX_CALL_FORWARD_PROBED: return M_FWD_PROBED;
     case TPX_CALL_BACKWARD_PROBED: return M_BWD_PROBED;
+    case TPX_CALL_RANGE_FINDER: return M_RANGE_FINDER;
     default: *ok = false; return M_FORWARD;
     }
 }
@@ -1023,7 +1049,7 @@ tpx_status job_init(GradJob &J, const tpx_grid *grid, const tpx_geom *geom, cons
     J.d = d_out ? d_out : (float *)(J.C.ws + J.C.plan.d);
     J.res = (float *)(J.C.ws + J.C.plan.res);
     J.ubar = (float *)(J.C.ws + J.C.plan.ubar);
-    J.Z = probe_matrix_dev(J.C, probe, &st);
+    J.Z = probe_matrix_dev(J.C, probe, d_obs, &st);
     if (st != TPX_OK) return st;
     st = fwd_begin(J.C, J.f, J.wavelet, J.d, nullptr, J.Z, probe->r, J.ubar, probe->dtt_side);
     if (st != TPX_OK) return st;
@@ -1105,7 +1131,11 @@ size_t tpx_workspace_bytes(int32_t call, const tpx_grid *grid, const tpx_geom *g
         tpx_status st = make_problem(grid, geom, &P);
         if (st != TPX_OK) return st;
         const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
-        if (probed && (st = check_probe(P, probe)) != TPX_OK) return st;
+        if ((probed || mode == M_RANGE_FINDER) && (st = check_probe(P, probe)) != TPX_OK) return st;
+        if (mode == M_RANGE_FINDER && probe->kind != TPX_PROBE_RANGE_FINDER)
+            return fail(TPX_E_INVAL, "TPX_CALL_RANGE_FINDER needs a range-finder probe");
+        if ((mode == M_FWD_PROBED || mode == M_BWD_PROBED) && probe->kind == TPX_PROBE_RANGE_FINDER)
+            return fail(TPX_E_INVAL, "range-finder probes need d_obs: pass tpx_range_finder_probes' Q as EXPLICIT");
         Tables T;
         if ((st = build_tables(P, grid, geom, &T)) != TPX_OK) return st;
         out = make_plan(P, mode, probe, T.blob.bytes.size()).total;
@@ -1239,7 +1269,7 @@ tpx_status tpx_forward_probed(const tpx_grid *grid, const tpx_geom *geom, const 
         if (st != TPX_OK) return st;
         const size_t need = align_up((size_t)C.P.L.S * probe->r * C.P.L.nphys * 4);
         if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
-        const float *Z = probe_matrix_dev(C, probe, &st);
+        const float *Z = probe_matrix_dev(C, probe, nullptr, &st);
         if (st != TPX_OK) return st;
         return run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, (float *)state, probe->dtt_side);
     });
@@ -1256,7 +1286,7 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
         const Layout &L = C.P.L;
         const size_t need = align_up((size_t)L.S * probe->r * L.nphys * 4);
         if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
-        const float *Z = probe_matrix_dev(C, probe, &st);
+        const float *Z = probe_matrix_dev(C, probe, nullptr, &st);
         if (st != TPX_OK) return st;
         AdjOut o;
         o.Z = Z;
@@ -1331,6 +1361,26 @@ tpx_status tpx_check_workspace(const void *ws, void *stream) {
         TPX_HIP(hipMemcpy(&flags, ws, sizeof flags, hipMemcpyDeviceToHost));
         if (flags & 1) return fail(TPX_E_NUMERIC, "the model holds a non-finite or non-positive value");
         if (flags & 2) return fail(TPX_E_CFL, "the model holds velocities above damp_vmax (dt may be unstable)");
+        return TPX_OK;
+    });
+}
+
+tpx_status tpx_range_finder_probes(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe,
+                                   const float *d_obs, float *Q, void *ws, size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if (!d_obs || !Q) return fail(TPX_E_INVAL, "d_obs and Q must not be NULL");
+        Problem P;
+        tpx_status st = make_problem(grid, geom, &P);
+        if (st != TPX_OK) return st;
+        if ((st = check_probe(P, probe)) != TPX_OK) return st;
+        if (probe->kind != TPX_PROBE_RANGE_FINDER) return fail(TPX_E_INVAL, "probe kind must be RANGE_FINDER");
+        const Plan plan = make_plan(P, M_RANGE_FINDER, probe, 0);
+        if (!ws || ws_bytes < plan.total) return fail(TPX_E_NOMEM, "workspace smaller than required");
+        unsigned char *w = (unsigned char *)ws;
+        const hipStream_t s = (hipStream_t)stream;
+        TPX_HIP(launch_probe_gen(TPX_PROBE_RADEMACHER, probe->r, probe->seed, P.nt, 0, P.L.S, Q, s));
+        TPX_HIP(launch_range_finder(P.L.S, P.nt, P.nrec, probe->r, d_obs, Q, (double *)(w + plan.rfW),
+                                    (double *)(w + plan.rfY), s));
         return TPX_OK;
     });
 }

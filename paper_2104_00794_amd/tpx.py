@@ -25,9 +25,9 @@ STATUS_NAMES = {0: "TPX_OK", 1: "TPX_E_INVAL", 2: "TPX_E_CFL", 3: "TPX_E_GEOM", 
                 5: "TPX_E_DEVICE", 6: "TPX_E_NUMERIC", 7: "TPX_E_STATE"}
 
 CALL_FORWARD, CALL_ADJOINT, CALL_GRADIENT_PROBED, CALL_GRADIENT_FULL, CALL_FORWARD_PROBED, \
-    CALL_BACKWARD_PROBED = range(6)
+    CALL_BACKWARD_PROBED, CALL_RANGE_FINDER = range(7)
 
-PROBE_KINDS = {"rademacher": 0, "gauss_b64": 1, "identity": 2, "explicit": 3}
+PROBE_KINDS = {"rademacher": 0, "gauss_b64": 1, "identity": 2, "explicit": 3, "range_finder": 4}
 
 
 class TpxError(RuntimeError):
@@ -87,6 +87,7 @@ def lib():
     L.tpx_forward_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp, sz, vp]
     L.tpx_backward_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp, vp, sz, vp]
     L.tpx_probe_matrix.argtypes = [P(_Probe), i32, i32, vp, vp]
+    L.tpx_range_finder_probes.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp]
     L.tpx_check_workspace.argtypes = [vp, vp]
     L.tpx_job_create.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, vp, vp, vp, sz, vp,
                                  P(ctypes.c_void_p)]
@@ -351,6 +352,19 @@ def backward_probed(grid: Grid, geom: Geometry, probe: Probe, m, grad_d, state, 
                                      grad_d.data_ptr(), state.data_ptr(), state.numel(), g.data_ptr(),
                                      ws.data_ptr(), ws.numel(), _stream(stream)))
     return g
+
+
+def range_finder_probes(grid: Grid, geom: Geometry, probe: Probe, d_obs, ws=None, stream=None):
+    """Q[S][nt][r] = qr(D D^T Z) per shot from the observed traces (Eq. 6); pass
+    it as ``Probe(kind="explicit", Z=Q, scale=1)`` to the split forward/backward."""
+    torch = _torch()
+    _dev_f32(d_obs, (geom.nshots, grid.nt, geom.nrec), "d_obs")
+    Q = torch.empty((geom.nshots, grid.nt, probe.r), dtype=torch.float32, device=d_obs.device)
+    ws = _ws(ws, CALL_RANGE_FINDER, grid, geom, probe, d_obs.device)
+    gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _check(lib().tpx_range_finder_probes(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), d_obs.data_ptr(),
+                                         Q.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return Q
 
 
 def probe_matrix(probe: Probe, nt: int, shot: int, device=None, stream=None):

@@ -96,3 +96,24 @@ def test_probe_side_validated():
     assert ok == tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4))
     with pytest.raises(tpx.TpxError):
         tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4, dtt_side=2))
+
+
+def test_range_finder_probe_validation_and_workspace():
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0]] * 2, [[[10.0 * i, 0, 20.0] for i in range(6)]] * 2)
+    p = tpx.Probe(kind="range_finder", r=4, seed=3)
+    # FP64 scratch: S*nrec*r + S*nt*r doubles (each region 256-byte aligned)
+    need = tpx.workspace_bytes(tpx.CALL_RANGE_FINDER, grid, geom, p)
+    assert need >= 8 * (2 * 6 * 4 + 2 * 100 * 4)
+    assert need < 8 * (2 * 6 * 4 + 2 * 100 * 4) + 1024
+    # gradient calls take the kind; r is bounded by nrec and 64
+    assert tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, p) > \
+        tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4))
+    for bad in (tpx.Probe(kind="range_finder", r=7), tpx.Probe(kind="range_finder", r=65)):
+        with pytest.raises(tpx.TpxError):
+            tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, bad)
+    # the split pair has no observed data
+    with pytest.raises(tpx.TpxError):
+        tpx.workspace_bytes(tpx.CALL_FORWARD_PROBED, grid, geom, p)
+    with pytest.raises(tpx.TpxError):
+        tpx.workspace_bytes(tpx.CALL_RANGE_FINDER, grid, geom, tpx.Probe(r=4))

@@ -388,3 +388,34 @@ def test_algorithm1_side_is_exact_with_identity_probes():
     res = d - cuda(dobs)
     g_split = tpx.backward_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), res, state)
     assert rel_l2(to_np(g_split), to_np(g_id)) <= 1e-6
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_range_finder_probes_match_oracle(ndim):
+    # Q = qr(D D^T Z) per shot (Eq. 6): the GPU's FP64 Householder factor spans
+    # the oracle's (NumPy) one; the probed gradient depends on Q Q^T only
+    _print_case("range_finder", ndim=ndim)
+    import torch
+    c = _grad_case(ndim)
+    dobs = c.dobs_oracle().astype(np.float32)
+    # r within the numerical rank of D D^T Z: beyond it Q's columns are an
+    # arbitrary orthonormal completion (the short 3D record reaches few
+    # receivers: its traces have only ~4 significant singular values)
+    r, seed = (6 if ndim == 2 else 3), 17
+    Qo = oracle.range_finder_probes(dobs, r, seed)
+    probe = tpx.Probe(kind="range_finder", r=r, seed=seed, block=13)
+    Qg = to_np(tpx.range_finder_probes(c.tgrid(), c.tgeom(), probe, cuda(dobs))).astype(np.float64)
+    for s in range(c.wl.nshots):
+        assert np.abs(Qg[s].T @ Qg[s] - np.eye(r)).max() <= 1e-6
+        assert np.linalg.norm(Qg[s] @ Qg[s].T - Qo[s] @ Qo[s].T) <= 1e-5 * np.sqrt(r)
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, kind="explicit", r=r, Z=Qo,
+                                      scale=1.0)
+    g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+    # the split forward/backward pair with the same Q as explicit probes
+    if ndim == 2:
+        pe = tpx.Probe(kind="explicit", r=r, Z=cuda(Qg.astype(np.float32)), scale=1.0, block=13)
+        d, state = tpx.forward_probed(c.tgrid(), c.tgeom(), pe, cuda(c.m0))
+        g_split = tpx.backward_probed(c.tgrid(), c.tgeom(), pe, cuda(c.m0), d - cuda(dobs), state)
+        assert torch.equal(g_split, g_g)
