@@ -82,7 +82,7 @@ def _load():
         lib.orc_adjoint.argtypes = [P(_Grid), P(_Geom), dp, dp, dp, dp]
         lib.orc_gradient_full.argtypes = [P(_Grid), P(_Geom), dp, dp, ctypes.c_int32, dp, dp, dp]
         lib.orc_gradient_probed.argtypes = [P(_Grid), P(_Geom), dp, dp, ctypes.c_int32, ctypes.c_int32,
-                                            ctypes.c_uint64, dp, ctypes.c_double, ctypes.c_int32,
+                                            ctypes.c_uint64, dp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
                                             P(ctypes.c_int64), ctypes.c_int64, dp, dp, dp]
         lib.orc_probe_matrix.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64, ctypes.c_int32,
                                          ctypes.c_int32, dp]
@@ -218,9 +218,12 @@ def gradient_full(grid: Grid, m, src_pos, rec_pos, wavelet, d_obs, form: int = 0
 
 
 def gradient_probed(grid: Grid, m, src_pos, rec_pos, wavelet, d_obs, kind="rademacher", r=8, seed=0,
-                    Z=None, scale=1.0, side=0, points=None, return_traces=False):
+                    Z=None, scale=1.0, side=0, imaging=0, points=None, return_traces=False):
     """Probed gradient (Eq. 4, Algorithm 1); returns (g~, J).
 
+    ``imaging``: 0 images the probed fields pointwise (Eq. 4); 1 takes the
+    inner product of their centred spatial gradients (Eq. 5 with D_x = grad;
+    zero on the outermost physical nodes).
     ``points``: optional flat physical indices; then g~ is returned only there.
     """
     lib = _load()
@@ -240,7 +243,7 @@ def gradient_probed(grid: Grid, m, src_pos, rec_pos, wavelet, d_obs, kind="radem
     J = np.zeros(1)
     dout = np.zeros((geo.c.nshots, grid.nt, geo.c.nrec)) if return_traces else None
     _check(lib.orc_gradient_probed(ctypes.byref(grid.c()), ctypes.byref(geo.c), _dp(_m(grid, m)), _dp(dobs),
-                                   kind_id, r, ctypes.c_uint64(seed), _dp(Zc), float(scale), side, pp, npts,
+                                   kind_id, r, ctypes.c_uint64(seed), _dp(Zc), float(scale), side, imaging, pp, npts,
                                    _dp(g), _dp(J), _dp(dout)))
     if return_traces:
         return g, float(J[0]), dout

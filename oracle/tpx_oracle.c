@@ -604,10 +604,35 @@ int orc_gradient_full(const orc_grid *g, const orc_geom *geo, const double *m, c
  *   side 0: probes u and the second time difference of lambda (default);
  *   side 1: probes the second time difference of u and lambda (as printed).
  * pts/npts: physical points at which g~ is computed (NULL = every point). */
+/* Inner product of the centred spatial gradients of two fields on the
+ * physical grid at node q = (x, y, z): sum over axes of
+ * (a[q+e] - a[q-e]) / (2h) * (b[q+e] - b[q-e]) / (2h); 0 on the outermost
+ * physical nodes. */
+static double grad_dot(const orc_grid *g, const double *a, const double *b, int64_t q) {
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2];
+    const int64_t x = q % nx, y = (q / nx) % ny, z = q / (nx * ny);
+    if (x == 0 || x == nx - 1 || z == 0 || z == nz - 1) return 0.0;
+    if (g->ndim == 3 && (y == 0 || y == ny - 1)) return 0.0;
+    const int64_t strides[3] = {1, nx, nx * ny};
+    const double ih2 = 1.0 / (2.0 * g->h);
+    double s = 0.0;
+    for (int a3 = 0; a3 < 3; ++a3) {
+        if (a3 == 1 && g->ndim == 2) continue;
+        const int64_t e = strides[a3];
+        s += ((a[q + e] - a[q - e]) * ih2) * ((b[q + e] - b[q - e]) * ih2);
+    }
+    return s;
+}
+
+/* imaging = 0: pointwise product of the probed fields (Eq. 4); imaging = 1:
+ * inner product of their spatial gradients (Eq. 5 with the space-only operator
+ * D_x = grad), which needs the whole physical grid (no point subset). */
 int orc_gradient_probed(const orc_grid *g, const orc_geom *geo, const double *m, const double *d_obs,
                         int32_t kind, int32_t r, uint64_t seed, const double *Zexp, double scale, int32_t side,
-                        const int64_t *pts_in, int64_t npts_in, double *grad, double *J, double *d_out) {
+                        int32_t imaging, const int64_t *pts_in, int64_t npts_in, double *grad, double *J,
+                        double *d_out) {
     if (!valid_grid(g) || !valid_geom(g, geo) || r < 1 || (side != 0 && side != 1)) return ORC_E_INVAL;
+    if ((imaging != 0 && imaging != 1) || (imaging == 1 && pts_in)) return ORC_E_INVAL;
     if (kind == ORC_PROBE_EXPLICIT && !Zexp) return ORC_E_INVAL;
     if (kind == ORC_PROBE_IDENTITY && r != g->nt) return ORC_E_INVAL;
     const int64_t nphys = nphys_total(g), nt = g->nt;
@@ -654,7 +679,10 @@ int orc_gradient_probed(const orc_grid *g, const orc_geom *geo, const double *m,
         if (st != ORC_OK) break;
         for (int64_t q = 0; q < npts; ++q) {
             double tr = 0.0;
-            for (int32_t j = 0; j < r; ++j) tr += ub[(int64_t)j * npts + q] * vb[(int64_t)j * npts + q];
+            for (int32_t j = 0; j < r; ++j) {
+                if (imaging == 0) tr += ub[(int64_t)j * npts + q] * vb[(int64_t)j * npts + q];
+                else tr += grad_dot(g, &ub[(int64_t)j * npts], &vb[(int64_t)j * npts], q);
+            }
             grad[q] -= c * tr;
         }
     }

@@ -177,3 +177,56 @@ def test_unbiased_with_closed_form_variance(kind, kappa):
     assert 0.8 < (sq / nseeds) / pred < 1.25, (sq / nseeds) / pred
     mean_err = float(np.sum((acc / nseeds - g) ** 2))
     assert 0.25 < mean_err / (pred / nseeds) < 4.0, mean_err / (pred / nseeds)
+
+
+# --------------------------------------------------------------------------- #
+# imaging conditions on the probed fields (Eq. 5)
+# --------------------------------------------------------------------------- #
+
+def _grad_dot(h, A, B):
+    """Centred-difference gradient inner product over the last 2 (2D) or 3 (3D)
+    axes, zero on the outermost nodes; written with array slices."""
+    nd = A.ndim - 1
+    out = np.zeros(A.shape)
+    inner = (slice(None),) + (slice(1, -1),) * nd
+    for ax in range(1, nd + 1):
+        hi = list(inner)
+        lo = list(inner)
+        hi[ax] = slice(2, None)
+        lo[ax] = slice(None, -2)
+        out[inner] += ((A[tuple(hi)] - A[tuple(lo)]) / (2 * h)) * ((B[tuple(hi)] - B[tuple(lo)]) / (2 * h))
+    return out
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_gradient_imaging_commutes_with_probing(ndim):
+    # Eq. 5: a space-only linear operator (here grad) applied to the r probed
+    # fields equals probing the operator applied to every snapshot
+    if ndim == 2:
+        wl = small_2d(nz=14, nx=17, nbl=4, nt=40, order=4, nshots=1, nrec=5)
+    else:
+        wl = small_3d(nz=10, ny=7, nx=9, nbl=3, nt=30, order=4, nshots=1, nrec=4)
+    grid, mt, m0, dobs = _setup(wl)
+    src, rec, wav = wl.src_pos(), wl.rec_pos(), wl.wavelet()
+    d, uh = oracle.forward(grid, m0, src, rec, wav, return_history=True)
+    _, lh = oracle.adjoint(grid, m0, src, rec, d - dobs, return_history=True)
+    shape = tuple(wl.shape)
+    u = uh[0]
+    lam = np.concatenate([lh[0], np.zeros((1,) + shape)])
+    a = u[1:]                                   # u^s, s = 1..nt-1
+    b = lam[0:-2] - 2 * lam[1:-1] + lam[2:]     # w^s
+    # exact imaging condition: grad applied to every pair of snapshots
+    exact = -np.sum(_grad_dot(wl.h, a, b), axis=0)
+    g_id, _ = oracle.gradient_probed(grid, m0, src, rec, wav, dobs, kind="identity", r=wl.nt, imaging=1)
+    np.testing.assert_allclose(g_id, exact, rtol=0, atol=1e-11 * np.abs(exact).max())
+    # random probes: grad of the probed fields == probed grad of the snapshots
+    r, seed = 5, 23
+    Z = oracle.probe_matrix("rademacher", r, seed, wl.nt, 0)[1:]          # rows s = 1..nt-1
+    U = np.einsum("sj,s...->j...", Z, a)
+    W = np.einsum("sj,s...->j...", Z, b)
+    probed = -np.sum(_grad_dot(wl.h, U, W), axis=0) / r
+    g_pr, _ = oracle.gradient_probed(grid, m0, src, rec, wav, dobs, kind="rademacher", r=r, seed=seed, imaging=1)
+    np.testing.assert_allclose(g_pr, probed, rtol=0, atol=1e-11 * np.abs(probed).max())
+    # and it differs from the pointwise imaging condition
+    g_pt, _ = oracle.gradient_probed(grid, m0, src, rec, wav, dobs, kind="rademacher", r=r, seed=seed)
+    assert np.abs(g_pt - g_pr).max() > 1e-3 * np.abs(g_pr).max()
