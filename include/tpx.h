@@ -127,6 +127,12 @@ typedef struct {
                              (u^{k+1} - 2 u^k + u^{k-1}) and vbar_j = sum_k Z[k,j]
                              lam^k (k = 0..nt-2).  Both are unbiased estimators of
                              the gradient of Eq. 3 and equal it for Z = I. */
+    int32_t imaging;   /* imaging condition applied to the probed fields:
+                          0: pointwise product, g = -c sum_j ubar_j vbar_j (Eq. 4);
+                          1: space-only linear operator D = grad applied to the
+                             probed fields (Eq. 5), g = -c sum_j grad ubar_j .
+                             grad vbar_j with centred differences, 0 on the
+                             outermost physical nodes; needs keep_vbar = 1. */
 } tpx_probe;
 
 /* Call identifiers for tpx_workspace_bytes. */

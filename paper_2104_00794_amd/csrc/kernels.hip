@@ -896,6 +896,41 @@ __global__ __launch_bounds__(256) void k_image_probed(int64_t nphys, int S, int 
     g[p] = acc;
 }
 
+// Imaging condition through a space-only linear operator (Eq. 5): the inner
+// product of the centred spatial gradients of the probed fields,
+// g = -c sum_shots sum_j sum_axes D ubar_j . D vbar_j, D f = (f[+e] - f[-e]) / 2h;
+// the outermost physical nodes get 0.
+__global__ __launch_bounds__(256) void k_image_graddot(int64_t nphys, int S, int r, float c, int ndim, int n0, int n1,
+                                                       int n2, float inv2h, const float *__restrict__ ubar,
+                                                       const float *__restrict__ vbar, float *__restrict__ g) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= nphys) return;
+    const int x = (int)(p % n0), y = (int)((p / n0) % n1), z = (int)(p / ((int64_t)n0 * n1));
+    const bool edge = x == 0 || x == n0 - 1 || z == 0 || z == n2 - 1 || (ndim == 3 && (y == 0 || y == n1 - 1));
+    float acc = 0.0f;
+    if (!edge) {
+        const int64_t ex = 1, ey = n0, ez = (int64_t)n0 * n1;
+        for (int s = 0; s < S; ++s) {
+            float tr = 0.0f;
+            for (int j = 0; j < r; ++j) {
+                const int64_t e = ((int64_t)s * r + j) * nphys + p;
+                tr += ((ubar[e + ex] - ubar[e - ex]) * inv2h) * ((vbar[e + ex] - vbar[e - ex]) * inv2h);
+                if (ndim == 3) tr += ((ubar[e + ey] - ubar[e - ey]) * inv2h) * ((vbar[e + ey] - vbar[e - ey]) * inv2h);
+                tr += ((ubar[e + ez] - ubar[e - ez]) * inv2h) * ((vbar[e + ez] - vbar[e - ez]) * inv2h);
+            }
+            acc -= c * tr;
+        }
+    }
+    g[p] = acc;
+}
+
+hipError_t launch_image_graddot(const Layout &L, double h, int r, float c, const float *ubar, const float *vbar,
+                                float *g, hipStream_t stream) {
+    hipLaunchKernelGGL(k_image_graddot, dim3((unsigned)((L.nphys + 255) / 256)), dim3(256), 0, stream, L.nphys, L.S,
+                       r, c, L.ndim, (int)L.n[0], (int)L.n[1], (int)L.n[2], (float)(0.5 / h), ubar, vbar, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_image_sum(const Layout &L, const float *gpart, float *g, hipStream_t stream) {
     hipLaunchKernelGGL(k_image_sum, dim3((unsigned)((L.nphys + 255) / 256)), dim3(256), 0, stream, L.nphys, L.S,
                        gpart, g);

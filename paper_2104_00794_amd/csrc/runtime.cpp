@@ -132,6 +132,7 @@ struct Problem {
     Physics ph;
     int nt;
     double dt;
+    double h;
     int nrec;
 };
 
@@ -201,6 +202,7 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
     P->ph.inv_nb = L.nb > 0 ? (float)(1.0 / L.nb) : 0.0f;
     P->nt = g->nt;
     P->dt = g->dt;
+    P->h = g->h;
     P->nrec = geo->nrec;
     return TPX_OK;
 }
@@ -457,6 +459,8 @@ tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     if (pr->kind == TPX_PROBE_EXPLICIT && !pr->Z) return fail(TPX_E_INVAL, "explicit probes need Z");
     if (pr->block < 0) return fail(TPX_E_INVAL, "block must be >= 0");
     if (pr->dtt_side != 0 && pr->dtt_side != 1) return fail(TPX_E_INVAL, "dtt_side must be 0 or 1");
+    if (pr->imaging != 0 && pr->imaging != 1) return fail(TPX_E_INVAL, "imaging must be 0 or 1");
+    if (pr->imaging == 1 && !pr->keep_vbar) return fail(TPX_E_INVAL, "the gradient imaging condition needs keep_vbar = 1");
     return TPX_OK;
 }
 
@@ -993,6 +997,12 @@ const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, const float *d_obs, t
     return Z;
 }
 
+// Imaging of the probed fields: pointwise (Eq. 4) or through the gradient (Eq. 5).
+hipError_t image_probed(const Ctx &C, const tpx_probe &pr, float c, const float *ubar, const float *vbar, float *g) {
+    if (pr.imaging == 1) return launch_image_graddot(C.P.L, C.P.h, pr.r, c, ubar, vbar, g, C.stream);
+    return launch_image_probed(C.P.L, pr.r, c, ubar, vbar, g, C.stream);
+}
+
 float probe_scale(const tpx_probe *pr) {
     if (pr->kind == TPX_PROBE_IDENTITY || pr->kind == TPX_PROBE_RANGE_FINDER) return 1.0f;
     if (pr->kind == TPX_PROBE_EXPLICIT) return (float)pr->scale;
@@ -1094,7 +1104,7 @@ tpx_status job_advance(GradJob &J, int64_t max_steps) {
         if (J.b.finished) {
             const Layout &L = J.C.P.L;
             TPX_HIP(prof(KIND_OTHER, J.C.stream, [&] {
-                return J.probe.keep_vbar ? launch_image_probed(L, J.probe.r, J.b.o.c, J.ubar, J.b.o.vbar, J.g, J.C.stream)
+                return J.probe.keep_vbar ? image_probed(J.C, J.probe, J.b.o.c, J.ubar, J.b.o.vbar, J.g)
                                          : launch_image_sum(L, J.b.o.gpart, J.g, J.C.stream);
             }));
             J.phase = 2;
@@ -1300,7 +1310,7 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
         st = run_adjoint(C, grad_d, o);
         if (st != TPX_OK) return st;
         TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
-            return probe->keep_vbar ? launch_image_probed(L, probe->r, o.c, o.ubar, o.vbar, g, C.stream)
+            return probe->keep_vbar ? image_probed(C, *probe, o.c, o.ubar, o.vbar, g)
                                     : launch_image_sum(L, o.gpart, g, C.stream);
         }));
         return TPX_OK;

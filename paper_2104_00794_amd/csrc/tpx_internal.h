@@ -152,6 +152,10 @@ hipError_t launch_accum_full(const Layout &L, const float *hist, const float *ri
 hipError_t launch_image_sum(const Layout &L, const float *gpart, float *g, hipStream_t stream);
 hipError_t launch_image_probed(const Layout &L, int r, float c, const float *ubar, const float *vbar, float *g,
                                hipStream_t stream);
+// g = -c sum_shot sum_j grad ubar_j . grad vbar_j (centred differences, grid step h;
+// 0 on the outermost physical nodes)
+hipError_t launch_image_graddot(const Layout &L, double h, int r, float c, const float *ubar, const float *vbar,
+                                float *g, hipStream_t stream);
 // Probes from the range of the data covariance: Z[S][nt][r] holds the shots'
 // Rademacher probes on entry and Q = qr(D D^T Z) on exit.  W (S*nrec*r) and Y
 // (S*nt*r) are FP64 scratch.  r <= 64, nt >= r.

@@ -51,7 +51,7 @@ class _Geom(ctypes.Structure):
 class _Probe(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("r", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("Z", ctypes.c_void_p), ("scale", ctypes.c_double), ("block", ctypes.c_int32),
-                ("keep_vbar", ctypes.c_int32), ("dtt_side", ctypes.c_int32)]
+                ("keep_vbar", ctypes.c_int32), ("dtt_side", ctypes.c_int32), ("imaging", ctypes.c_int32)]
 
 
 _lib = None
@@ -189,6 +189,7 @@ class Probe:
     block: int = 0
     keep_vbar: bool = False
     dtt_side: int = 0                # 1: the second time difference on the forward side (Algorithm 1)
+    imaging: int = 0                 # 1: gradient inner product of the probed fields (Eq. 5); keep_vbar=True
 
     def c(self) -> _Probe:
         p = _Probe()
@@ -200,6 +201,7 @@ class Probe:
         p.block = int(self.block)
         p.keep_vbar = 1 if self.keep_vbar else 0
         p.dtt_side = int(self.dtt_side)
+        p.imaging = int(self.imaging)
         return p
 
 

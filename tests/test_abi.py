@@ -117,3 +117,12 @@ def test_range_finder_probe_validation_and_workspace():
         tpx.workspace_bytes(tpx.CALL_FORWARD_PROBED, grid, geom, p)
     with pytest.raises(tpx.TpxError):
         tpx.workspace_bytes(tpx.CALL_RANGE_FINDER, grid, geom, tpx.Probe(r=4))
+
+
+def test_gradient_imaging_condition_needs_vbar():
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]])
+    tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=4, imaging=1, keep_vbar=True))
+    for bad in (tpx.Probe(r=4, imaging=1), tpx.Probe(r=4, imaging=2, keep_vbar=True)):
+        with pytest.raises(tpx.TpxError):
+            tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, bad)

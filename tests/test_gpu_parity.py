@@ -419,3 +419,20 @@ def test_range_finder_probes_match_oracle(ndim):
         d, state = tpx.forward_probed(c.tgrid(), c.tgeom(), pe, cuda(c.m0))
         g_split = tpx.backward_probed(c.tgrid(), c.tgeom(), pe, cuda(c.m0), d - cuda(dobs), state)
         assert torch.equal(g_split, g_g)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_gradient_imaging_condition_matches_oracle(ndim):
+    # Eq. 5: the space-only operator grad applied to the r probed fields
+    _print_case("imaging_graddot", ndim=ndim)
+    c = _grad_case(ndim)
+    dobs = c.dobs_oracle()
+    r, seed = 6, 29
+    g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=r, seed=seed, imaging=1)
+    probe = tpx.Probe(r=r, seed=seed, block=13, keep_vbar=True, imaging=1)
+    g_g, _ = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    # the split pair images the same way
+    d, state = tpx.forward_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0))
+    g_split = tpx.backward_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), d - cuda(dobs), state)
+    assert rel_l2(to_np(g_split), g_o) <= TOL
