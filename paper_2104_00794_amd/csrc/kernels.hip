@@ -334,37 +334,39 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
 // come from per-thread register queues of 2R+1 values; x/y neighbours from
 // the current plane staged in LDS (double-buffered, one barrier per plane).
 // The halo of the next plane is prefetched into registers while the current
-// plane is computed.  Logical blocks are numbered XCD-aware as in 2D; only
-// nodes of the padded box are read.
+// plane is computed.  Every lane's byte offsets within a plane are fixed for
+// the whole march and the plane offset is wave-uniform, so the raw buffer
+// accesses need no vector address arithmetic.  Columns whose halo lies in
+// the padded box and whose nodes are undamped take a path without clamping,
+// masking or damping terms.  u^{k-1}, beta and u^{k+1} are streamed past the
+// caches (nontemporal).  Logical blocks are numbered XCD-aware as in 2D.
 // ---------------------------------------------------------------------------
-template <int R>
-__global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
+constexpr int kBufNT = 2;   // cache-policy bit of a streamed (nontemporal) buffer access
+
+template <int R, bool FAST>
+__device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot, int bx,
+                                            int by, int zc, float (*plane_t)[T3Y + 2 * R][T3X + 2 * R]) {
 #pragma clang fp contract(off)
     constexpr int W = T3X + 2 * R;
-    constexpr int H = T3Y + 2 * R;   // 16 rows for R = 4
-    __shared__ float plane_t[2][H][W];
-
     const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
-    const int nzc = (int)((L.P[2] + T3Z - 1) / T3Z);
-    const int lid = xcd_logical_block(ntx * nty * nzc * L.S);
-    if (lid < 0) return;
-    const int bx = lid % ntx, by = (lid / ntx) % nty, zc = (lid / (ntx * nty)) % nzc, shot = lid / (ntx * nty * nzc);
-
-    const int tid = threadIdx.x;
-    const int lx = tid & 63, ly = tid >> 6;
+    const int lx = threadIdx.x & 63;
+    const int ly = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int x0 = bx * T3X, y0 = by * T3Y, zc0 = zc * T3Z;
     const int x = x0 + lx;
     const int ya = y0 + ly, yb = y0 + ly + 4;            // the two y rows of this thread
     const int G0 = (int)L.G[0], PL = (int)(L.G[0] * L.G[1]);
     const int P0 = (int)L.P[0], P1 = (int)L.P[1], P2 = (int)L.P[2], oy = (int)L.oy;
-    const float *cur = a.cur + shot * L.shot_floats + XO;
-    const float *prev = a.prev + shot * L.shot_floats + XO;
-    const float *beta = a.beta + XO;
-    float *next = a.next + shot * L.shot_floats + XO;
+    const uint32_t span = (uint32_t)(L.shot_floats * 4);
+    const int64_t so = shot * L.shot_floats + XO;
+    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cur + so, span), rp = buf_rsrc(a.prev + so, span);
+    const __amdgpu_buffer_rsrc_t rb = buf_rsrc(a.beta + XO, span), rn = buf_rsrc(a.next + so, span);
+    auto plane = [&](int z) { return (uint32_t)((FAST ? z : clampi(z, 0, P2 - 1)) + R) * (uint32_t)PL * 4u; };
+    auto lane = [&](int y, int xx) {   // byte offset of (y, x) within a plane
+        return 4u * (uint32_t)(((FAST ? y : clampi(y, 0, P1 - 1)) + oy) * G0 + (FAST ? xx : clampi(xx, 0, P0 - 1)));
+    };
 
-    const bool oa = x < P0 && ya < P1, ob = x < P0 && yb < P1;       // columns inside the box
-    const bool ca = oa, cb = ob;
-    const int cola = (ya + oy) * G0 + x, colb = (yb + oy) * G0 + x;  // + (z + R) * PL
+    const bool oa = FAST || (x < P0 && ya < P1), ob = FAST || (x < P0 && yb < P1);   // columns inside the box
+    const uint32_t va = lane(ya, x), vb = lane(yb, x);
 
     // halo of a plane: rows ly and ly + 12 (y0 - R + ly, y0 + 8 + ly), all 72 columns;
     // rows 4 + ly and 8 + ly (the centre rows) only their x-halo columns.
@@ -372,46 +374,54 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
     const int hxa = x0 - R + lx;                     // columns 0..63 of the staged row
     const int hxb = x0 - R + 64 + lx;                // columns 64..71 (lanes < 2R)
     const int hxc = lx < R ? x0 - R + lx : x0 + T3X + (lx - R);  // x-halo of the centre rows (lanes < 2R)
-    const bool y0ok = hy0 >= 0 && hy0 < P1, y1ok = hy1 < P1;
-    const bool xaok = hxa >= 0 && hxa < P0, xbok = lx < 2 * R && hxb < P0;
-    const bool xcok = lx < 2 * R && hxc >= 0 && hxc < P0;
+    const bool y0ok = FAST || (hy0 >= 0 && hy0 < P1), y1ok = FAST || hy1 < P1;
+    const bool xaok = FAST || (hxa >= 0 && hxa < P0);
+    const bool xbok = lx < 2 * R && (FAST || hxb < P0), xcok = lx < 2 * R && (FAST || (hxc >= 0 && hxc < P0));
+    const uint32_t h0 = lane(hy0, hxa), h1 = lane(hy0, lx < 2 * R ? hxb : hxa), h2 = lane(hy1, hxa);
+    const uint32_t h3 = lane(hy1, lx < 2 * R ? hxb : hxa);
+    const uint32_t h4 = lane(ya, lx < 2 * R ? hxc : x), h5 = lane(yb, lx < 2 * R ? hxc : x);
+    const bool h4ok = xcok && (FAST || ya < P1), h5ok = xcok && (FAST || yb < P1);
     auto load_halo = [&](int z, float h[6]) {
-        const int zo = (z + R) * PL;
-        h[0] = (y0ok && xaok) ? cur[zo + (hy0 + oy) * G0 + hxa] : 0.0f;
-        h[1] = (y0ok && xbok) ? cur[zo + (hy0 + oy) * G0 + hxb] : 0.0f;
-        h[2] = (y1ok && xaok) ? cur[zo + (hy1 + oy) * G0 + hxa] : 0.0f;
-        h[3] = (y1ok && xbok) ? cur[zo + (hy1 + oy) * G0 + hxb] : 0.0f;
-        h[4] = (xcok && ya < P1) ? cur[zo + (ya + oy) * G0 + hxc] : 0.0f;
-        h[5] = (xcok && yb < P1) ? cur[zo + (yb + oy) * G0 + hxc] : 0.0f;
+        const uint32_t zo = plane(z);
+        const float v0 = buf_load(rc, h0, zo), v1 = buf_load(rc, h1, zo), v2 = buf_load(rc, h2, zo);
+        const float v3 = buf_load(rc, h3, zo), v4 = buf_load(rc, h4, zo), v5 = buf_load(rc, h5, zo);
+        h[0] = (y0ok && xaok) ? v0 : 0.0f;
+        h[1] = (y0ok && xbok) ? v1 : 0.0f;
+        h[2] = (y1ok && xaok) ? v2 : 0.0f;
+        h[3] = (y1ok && xbok) ? v3 : 0.0f;
+        h[4] = h4ok ? v4 : 0.0f;
+        h[5] = h5ok ? v5 : 0.0f;
     };
 
     float qa[2 * R + 1], qb[2 * R + 1];
 #pragma unroll
     for (int i = 0; i < 2 * R; ++i) {
         const int z = zc0 - R + i;
-        const bool zin = z >= 0 && z < P2;
-        qa[i] = (ca && zin) ? cur[(z + R) * PL + cola] : 0.0f;
-        qb[i] = (cb && zin) ? cur[(z + R) * PL + colb] : 0.0f;
+        const bool zin = FAST || (z >= 0 && z < P2);
+        const uint32_t zo = plane(z);
+        const float va_ = buf_load(rc, va, zo), vb_ = buf_load(rc, vb, zo);
+        qa[i] = (oa && zin) ? va_ : 0.0f;
+        qb[i] = (ob && zin) ? vb_ : 0.0f;
     }
     float h[6];
     load_halo(zc0, h);
-    const float hx = layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
-    const float hxy_a = hx + layer_frac2(ya, (int)L.n[1], L.nb, ph.inv_nb);
-    const float hxy_b = hx + layer_frac2(yb, (int)L.n[1], L.nb, ph.inv_nb);
+    const float hx = FAST ? 0.0f : layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
+    const float hxy_a = FAST ? 0.0f : hx + layer_frac2(ya, (int)L.n[1], L.nb, ph.inv_nb);
+    const float hxy_b = FAST ? 0.0f : hx + layer_frac2(yb, (int)L.n[1], L.nb, ph.inv_nb);
 
     for (int lz = 0; lz < T3Z; ++lz) {
         const int z = zc0 + lz;
-        if (z >= P2) break;
-        const int zo = (z + R) * PL;
-        const bool zr = z + R < P2;
-        qa[2 * R] = (ca && zr) ? cur[zo + R * PL + cola] : 0.0f;
-        qb[2 * R] = (cb && zr) ? cur[zo + R * PL + colb] : 0.0f;
-        // u^{k-1} and beta are read once and u^{k+1} written once per launch:
-        // streamed past the caches (measured: less traffic than cached access)
-        const float pa = oa ? __builtin_nontemporal_load(prev + zo + cola) : 0.0f;
-        const float pb = ob ? __builtin_nontemporal_load(prev + zo + colb) : 0.0f;
-        const float ba = oa ? __builtin_nontemporal_load(beta + zo + cola) : 0.0f;
-        const float bb = ob ? __builtin_nontemporal_load(beta + zo + colb) : 0.0f;
+        if (!FAST && z >= P2) break;
+        const uint32_t zo = plane(z), zr_o = plane(z + R);
+        const bool zr = FAST || z + R < P2;
+        const float qa_ = buf_load(rc, va, zr_o), qb_ = buf_load(rc, vb, zr_o);
+        qa[2 * R] = (oa && zr) ? qa_ : 0.0f;
+        qb[2 * R] = (ob && zr) ? qb_ : 0.0f;
+        const float pa_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)va, (int)zo, kBufNT));
+        const float pb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)vb, (int)zo, kBufNT));
+        const float ba_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)va, (int)zo, kBufNT));
+        const float bb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)vb, (int)zo, kBufNT));
+        const float pa = oa ? pa_ : 0.0f, pb = ob ? pb_ : 0.0f, ba = oa ? ba_ : 0.0f, bb = ob ? bb_ : 0.0f;
 
         float(*pt)[W] = plane_t[lz & 1];
         pt[ly][lx] = h[0];
@@ -437,7 +447,7 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
             }
         }
         __syncthreads();
-        if (z + 1 < P2 && lz + 1 < T3Z) load_halo(z + 1, h);   // prefetch, overlaps the compute below
+        if (lz + 1 < T3Z && (FAST || z + 1 < P2)) load_halo(z + 1, h);   // prefetch, overlaps the compute below
 
         float lapa = 3.0f * ph.c[0] * qa[R], lapb = 3.0f * ph.c[0] * qb[R];
 #pragma unroll
@@ -449,15 +459,39 @@ __global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph
                                                (pt[R + 4 + ly - k][R + lx] + pt[R + 4 + ly + k][R + lx]) + (qb[R - k] + qb[R + k]),
                                   lapb);
         }
-        const float hz = layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb);
-        if (oa) __builtin_nontemporal_store(leapfrog(qa[R], pa, ba, lapa, sa, ph.hd_max * (hxy_a + hz)), next + zo + cola);
-        if (ob) __builtin_nontemporal_store(leapfrog(qb[R], pb, bb, lapb, sbv, ph.hd_max * (hxy_b + hz)), next + zo + colb);
+        float na, nb_;
+        if (FAST) {
+            na = leapfrog0(qa[R], pa, ba, lapa, sa);
+            nb_ = leapfrog0(qb[R], pb, bb, lapb, sbv);
+        } else {
+            const float hz = layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb);
+            na = leapfrog(qa[R], pa, ba, lapa, sa, ph.hd_max * (hxy_a + hz));
+            nb_ = leapfrog(qb[R], pb, bb, lapb, sbv, ph.hd_max * (hxy_b + hz));
+        }
+        if (oa) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, na), rn, (int)va, (int)zo, kBufNT);
+        if (ob) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, nb_), rn, (int)vb, (int)zo, kBufNT);
 #pragma unroll
         for (int i = 0; i < 2 * R; ++i) {
             qa[i] = qa[i + 1];
             qb[i] = qb[i + 1];
         }
     }
+}
+
+template <int R>
+__global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
+    __shared__ float plane_t[2][T3Y + 2 * R][T3X + 2 * R];
+    const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
+    const int nzc = (int)((L.P[2] + T3Z - 1) / T3Z);
+    const int lid = xcd_logical_block(ntx * nty * nzc * L.S);
+    if (lid < 0) return;
+    const int bx = lid % ntx, by = (lid / ntx) % nty, zc = (lid / (ntx * nty)) % nzc, shot = lid / (ntx * nty * nzc);
+    const int x0 = bx * T3X, y0 = by * T3Y, zc0 = zc * T3Z, nb = L.nb;
+    // interior column: every node undamped and every read inside the padded box
+    const bool fast = x0 - R >= nb && x0 + T3X + R <= nb + (int)L.n[0] && y0 - R >= nb &&
+                      y0 + T3Y + R <= nb + (int)L.n[1] && zc0 - R >= nb && zc0 + T3Z + R <= nb + (int)L.n[2];
+    if (fast) step3d_body<R, true>(L, ph, a, shot, bx, by, zc, plane_t);
+    else step3d_body<R, false>(L, ph, a, shot, bx, by, zc, plane_t);
 
     const int per_shot = ntx * nty * nzc, bis = (zc * nty + by) * ntx + bx;
     if (a.do_sample) sample_points<8>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bis, per_shot);

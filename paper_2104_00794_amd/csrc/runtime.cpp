@@ -179,8 +179,8 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
     L.nphys = L.n[0] * L.n[1] * L.n[2];
     L.npad = L.P[0] * L.P[1] * L.P[2];
     if (L.shot_floats >= (int64_t)1 << 31) return fail(TPX_E_INVAL, "one shot's field exceeds 2^31 floats");
-    // the 2D step kernels address one shot's field with 32-bit byte offsets
-    if (L.ndim == 2 && L.shot_floats >= (int64_t)1 << 30) return fail(TPX_E_INVAL, "one 2D shot field exceeds 2^30 floats");
+    // the step kernels address one shot's field with 32-bit byte offsets
+    if (L.shot_floats >= (int64_t)1 << 30) return fail(TPX_E_INVAL, "one shot's field exceeds 2^30 floats");
     if (L.ndim == 2) {
         L.tile[0] = t2x(L.R); L.tile[1] = 1; L.tile[2] = T2Z;
         L.map[0] = 64; L.map[1] = 1; L.map[2] = T2Z + 2 * L.R;
