@@ -434,7 +434,7 @@ int ring_slots(int b, bool overlap) { return overlap ? 2 * b + 3 : b + 2; }
 int default_block(const Layout &L, int nt, bool overlap) {
     const double slot_bytes = (double)L.slot_floats * 4.0;
     const double cap = 48e9;
-    int b = 128;
+    int b = 256;
     while (b > 16 && ring_slots(b, overlap) * slot_bytes > cap) b /= 2;
     if (b > nt - 1) b = nt - 1;
     if (b < 1) b = 1;
