@@ -143,7 +143,8 @@ enum {
     TPX_CALL_GRADIENT_FULL = 3,
     TPX_CALL_FORWARD_PROBED = 4,
     TPX_CALL_BACKWARD_PROBED = 5,
-    TPX_CALL_RANGE_FINDER = 6
+    TPX_CALL_RANGE_FINDER = 6,
+    TPX_CALL_OBJECTIVE = 7
 };
 
 /* Device workspace (bytes) that `call` needs for this problem; 0 on invalid
@@ -158,6 +159,14 @@ size_t tpx_state_bytes(const tpx_grid *grid, const tpx_geom *geom, const tpx_pro
 /* Forward modelling F(m; q), Eq. (2):  d[S][nt][nrec] (device). */
 tpx_status tpx_forward(const tpx_grid *grid, const tpx_geom *geom, const float *m, float *d,
                        void *ws, size_t ws_bytes, void *stream);
+
+/* Objective of Eq. (2) at m: forward modelling, then J = 1/2 ||F(m; q) - d_obs||^2
+ * summed over every trace sample (FP64 partial sums in a fixed order, so the
+ * value is run-to-run identical).  J is one device double; d_out (device
+ * [S][nt][nrec], may be NULL) receives F(m; q).  This is the function value
+ * that a line search along a model update needs, without back-propagation. */
+tpx_status tpx_objective(const tpx_grid *grid, const tpx_geom *geom, const float *m, const float *d_obs,
+                         double *J, float *d_out, void *ws, size_t ws_bytes, void *stream);
 
 /* Adjoint of the source-to-trace map: q_adj[S][nt] = F^T d_in (device),
  * q_adj^k = dt^2 S lambda^k.  <F q, d> = <q, F^T d> to rounding. */

@@ -447,7 +447,7 @@ struct Plan {
     bool overlap;
 };
 
-enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED, M_RANGE_FINDER };
+enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED, M_RANGE_FINDER, M_OBJECTIVE };
 
 tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     if (!pr) return fail(TPX_E_INVAL, "probe must not be NULL for probed calls");
@@ -476,14 +476,15 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     }
     const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
     const int r = probed ? pr->r : 0;
-    p.overlap = g_overlap.load() != 0 && mode != M_FORWARD && mode != M_ADJOINT;
+    const bool plain = mode == M_FORWARD || mode == M_ADJOINT || mode == M_OBJECTIVE;
+    p.overlap = g_overlap.load() != 0 && !plain;
     p.block = default_block(L, P.nt, p.overlap);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
     // without contractions the ring holds the levels one launch touches: three,
     // four for two fused steps (2D).  With contractions a launch never crosses a
     // block end, so one block plus two levels suffices.
-    p.nslots = (mode == M_FORWARD || mode == M_ADJOINT) ? (P.L.ndim == 2 ? 4 : 3) : ring_slots(p.block, p.overlap);
+    p.nslots = plain ? (P.L.ndim == 2 ? 4 : 3) : ring_slots(p.block, p.overlap);
     const size_t slot = (size_t)L.slot_floats * 4;
     const size_t ntr = (size_t)L.S * P.nt * P.nrec;
     size_t o = 0;
@@ -508,7 +509,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     if ((mode == M_GRAD_PROBED || mode == M_BWD_PROBED) && keep_v) p.vbar = take((size_t)L.S * r * L.nphys * 4);
     if (mode == M_GRAD_FULL || ((mode == M_GRAD_PROBED || mode == M_BWD_PROBED) && !keep_v))
         p.gpart = take((size_t)L.S * L.nphys * 4);
-    if (mode == M_GRAD_PROBED || mode == M_GRAD_FULL) {
+    if (mode == M_GRAD_PROBED || mode == M_GRAD_FULL || mode == M_OBJECTIVE) {
         p.res = take(ntr * 4);
         p.d = take(ntr * 4);
     }
@@ -1019,6 +1020,7 @@ Mode mode_of(int32_t call, bool *ok) {
     case TPX_CALL_FORWARD_PROBED: return M_FWD_PROBED;
     case TPX_CALL_BACKWARD_PROBED: return M_BWD_PROBED;
     case TPX_CALL_RANGE_FINDER: return M_RANGE_FINDER;
+    case TPX_CALL_OBJECTIVE: return M_OBJECTIVE;
     default: *ok = false; return M_FORWARD;
     }
 }
@@ -1175,6 +1177,25 @@ tpx_status tpx_forward(const tpx_grid *grid, const tpx_geom *geom, const float *
         tpx_status st = setup(C, grid, geom, nullptr, M_FORWARD, m, ws, ws_bytes, stream);
         if (st != TPX_OK) return st;
         return run_forward(C, geom->wavelet, d, nullptr, nullptr, 0, nullptr);
+    });
+}
+
+tpx_status tpx_objective(const tpx_grid *grid, const tpx_geom *geom, const float *m, const float *d_obs, double *J,
+                         float *d_out, void *ws, size_t ws_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        if ((!d_obs && geom && geom->nrec > 0) || !J) return fail(TPX_E_INVAL, "d_obs and J must not be NULL");
+        Ctx C;
+        tpx_status st = setup(C, grid, geom, nullptr, M_OBJECTIVE, m, ws, ws_bytes, stream);
+        if (st != TPX_OK) return st;
+        float *d = d_out ? d_out : (float *)(C.ws + C.plan.d);
+        st = run_forward(C, geom->wavelet, d, nullptr, nullptr, 0, nullptr);
+        if (st != TPX_OK) return st;
+        const int64_t ntr = (int64_t)C.P.L.S * C.P.nt * C.P.nrec;
+        TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
+            return launch_residual(d, d_obs, (float *)(C.ws + C.plan.res), ntr, (double *)(C.ws + C.plan.parts),
+                                   residual_parts(ntr), J, C.stream);
+        }));
+        return TPX_OK;
     });
 }
 

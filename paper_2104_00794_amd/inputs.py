@@ -224,10 +224,18 @@ def workload(name: str) -> Workload:
         return Workload(name, (301, 401, 401), 12.5, 8, 1.25, 2001, 0.012, 1.5, 4.0,
                         r=32, probe="rademacher", probe_seed=32, model_seed=31, smooth_sigma=10.0,
                         src=[(2500.0, 2500.0, 50.0)], rec=_grid_spread(0.0, 5000.0, 25.0, 50.0))
+    if name == "f4_fwi_2d":
+        # The inversion experiment's shape on C1's grid and model: 49 shots 200 m
+        # apart at 50 m depth, ocean-bottom receivers 50 m apart at 500 m depth,
+        # 8 Hz Ricker, 3 s records (Example section), r = 16.
+        return Workload(name, (301, 801), 12.5, 8, 1.25, 2401, 0.008, 1.5, 4.5,
+                        r=16, probe="rademacher", probe_seed=42, model_seed=11, smooth_sigma=10.0,
+                        src=[(200.0 * (i + 1), 0.0, 50.0) for i in range(49)],
+                        rec=_line(0.0, 10000.0, 50.0, 0.0, 500.0))
     raise KeyError(name)
 
 
-WORKLOADS = ("c0_two_layer_2d", "c1_layered_2d_16shots", "c2_autograd_2d", "c3_layered_3d")
+WORKLOADS = ("c0_two_layer_2d", "c1_layered_2d_16shots", "c2_autograd_2d", "c3_layered_3d", "f4_fwi_2d")
 
 
 def small_2d(nz=40, nx=48, h=10.0, order=8, nt=180, nbl=6, nshots=2, nrec=9, seed=5, r=8,

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "TPX_OK", 1: "TPX_E_INVAL", 2: "TPX_E_CFL", 3: "TPX_E_GEOM", 
                 5: "TPX_E_DEVICE", 6: "TPX_E_NUMERIC", 7: "TPX_E_STATE"}
 
 CALL_FORWARD, CALL_ADJOINT, CALL_GRADIENT_PROBED, CALL_GRADIENT_FULL, CALL_FORWARD_PROBED, \
-    CALL_BACKWARD_PROBED, CALL_RANGE_FINDER = range(7)
+    CALL_BACKWARD_PROBED, CALL_RANGE_FINDER, CALL_OBJECTIVE = range(8)
 
 PROBE_KINDS = {"rademacher": 0, "gauss_b64": 1, "identity": 2, "explicit": 3, "range_finder": 4}
 
@@ -82,6 +82,7 @@ def lib():
     L.tpx_state_bytes.restype = sz
     L.tpx_forward.argtypes = [P(_Grid), P(_Geom), vp, vp, vp, sz, vp]
     L.tpx_adjoint.argtypes = [P(_Grid), P(_Geom), vp, vp, vp, vp, sz, vp]
+    L.tpx_objective.argtypes = [P(_Grid), P(_Geom), vp, vp, vp, vp, vp, sz, vp]
     L.tpx_gradient_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, vp, vp, vp, sz, vp]
     L.tpx_gradient_full.argtypes = [P(_Grid), P(_Geom), vp, vp, vp, vp, vp, vp, sz, vp]
     L.tpx_forward_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp, sz, vp]
@@ -102,8 +103,8 @@ def lib():
     L.tpx_profile_enable.argtypes = [i32]
     L.tpx_profile_enable.restype = None
     L.tpx_profile_read.argtypes = [i32, P(ctypes.c_double), P(ctypes.c_int64)]
-    for name in ("tpx_forward", "tpx_adjoint", "tpx_gradient_probed", "tpx_gradient_full", "tpx_forward_probed",
-                 "tpx_backward_probed", "tpx_probe_matrix", "tpx_check_workspace", "tpx_profile_read",
+    for name in ("tpx_forward", "tpx_objective", "tpx_adjoint", "tpx_gradient_probed", "tpx_gradient_full",
+                 "tpx_forward_probed", "tpx_backward_probed", "tpx_probe_matrix", "tpx_check_workspace", "tpx_profile_read",
                  "tpx_job_create", "tpx_job_advance", "tpx_job_progress"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -276,6 +277,21 @@ def forward(grid: Grid, geom: Geometry, m, ws=None, stream=None):
     _check(lib().tpx_forward(ctypes.byref(g), ctypes.byref(ge), m.data_ptr(), d.data_ptr(), ws.data_ptr(),
                              ws.numel(), _stream(stream)))
     return d
+
+
+def objective(grid: Grid, geom: Geometry, m, d_obs, ws=None, stream=None, J_out=None, return_traces: bool = False):
+    """J = 1/2 ||F(m) - d_obs||^2 (Eq. 2) as a device double [1]: returns J[, d]."""
+    torch = _torch()
+    _dev_f32(m, grid.shape, "m")
+    _dev_f32(d_obs, (geom.nshots, grid.nt, geom.nrec), "d_obs")
+    J = J_out if J_out is not None else torch.empty(1, dtype=torch.float64, device=m.device)
+    d = torch.empty((geom.nshots, grid.nt, geom.nrec), dtype=torch.float32, device=m.device) if return_traces \
+        else None
+    ws = _ws(ws, CALL_OBJECTIVE, grid, geom, None, m.device)
+    g, ge = grid.c(), geom.c()
+    _check(lib().tpx_objective(ctypes.byref(g), ctypes.byref(ge), m.data_ptr(), d_obs.data_ptr(), J.data_ptr(),
+                               d.data_ptr() if d is not None else None, ws.data_ptr(), ws.numel(), _stream(stream)))
+    return (J, d) if return_traces else J
 
 
 def adjoint(grid: Grid, geom: Geometry, m, d_in, ws=None, stream=None):

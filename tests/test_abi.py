@@ -126,3 +126,18 @@ def test_gradient_imaging_condition_needs_vbar():
     for bad in (tpx.Probe(r=4, imaging=1), tpx.Probe(r=4, imaging=2, keep_vbar=True)):
         with pytest.raises(tpx.TpxError):
             tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, bad)
+
+
+def test_objective_workspace_and_null_arguments():
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0], [200.0, 0, 50.0]], [[[10.0, 0, 20.0]] * 3] * 2)
+    fwd = tpx.workspace_bytes(tpx.CALL_FORWARD, grid, geom)
+    obj = tpx.workspace_bytes(tpx.CALL_OBJECTIVE, grid, geom)
+    # forward ring plus the traces and residuals (2 x S*nt*nrec floats)
+    assert obj >= fwd + 2 * 4 * 2 * 100 * 3
+    L = tpx.lib()
+    g, ge = grid.c(), geom.c()
+    ge.wavelet = 0x1000
+    # J must not be NULL; nothing is launched
+    assert L.tpx_objective(ctypes.byref(g), ctypes.byref(ge), 0x1000, 0x2000, None, None, 0x3000, obj,
+                           None) == tpx.E_INVAL
