@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--keep-vbar", action="store_true", help="accumulate vbar instead of folding it")
     ap.add_argument("--overlap", action="store_true",
                     help="run the probe contractions on the auxiliary stream, overlapping the next time block")
+    ap.add_argument("--matrix-cores", type=int, default=None, choices=[0, 1, 2],
+                    help="probe contractions on the matrix cores: 0 never, 1 for r >= 32 (library default), 2 always")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (for HBM counter calibration)")
     ap.add_argument("--nt", type=int, default=None, help="override the record length (profiling runs)")
@@ -88,6 +90,8 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}), flush=True)
         return
     tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 1 if args.overlap else 0)
+    if args.matrix_cores is not None:
+        tpx.set_option(tpx.OPT_MATRIX_CORES, args.matrix_cores)
     if args.serving:
         return serving(args, dev)
 
@@ -204,6 +208,7 @@ def main():
                    "space_order": wl.order, "shots": S, "nt": nt, "nbl": wl.nbl, "r": r, "probe": kind,
                    "block": args.block or "default", "keep_vbar": bool(args.keep_vbar),
                    "overlap_contractions": bool(tpx.get_option(tpx.OPT_OVERLAP_CONTRACTIONS)),
+                   "matrix_core_contractions": matrix_core_use(kind, r, bool(args.keep_vbar)),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
         "host_enqueue_ms": round(host_enqueue_ms, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
@@ -288,6 +293,17 @@ def cpu_baseline(wl, r, kind, nt_sample, shots, d_obs):
             "seconds": round(dt, 2),
             "sample": "%d of %d shots, first %d of %d time steps, r=%d %s, same grid; FP64 C oracle with OpenMP"
                       % (sample.nshots, wl.nshots, sample.nt, wl.nt, r, kind)}
+
+
+def matrix_core_use(kind: str, r: int, keep_vbar: bool) -> str:
+    """Which contractions run on the matrix cores under the library option."""
+    opt = tpx.get_option(tpx.OPT_MATRIX_CORES)
+    if kind not in ("rademacher", "gauss_b64") or r % 16 != 0 or opt == 0:
+        return "none"
+    accum = opt == 2 or r >= 64
+    fold = not keep_vbar and (opt == 2 or r >= 32)
+    parts = [p for p, on in (("ubar", accum), ("vbar", accum and keep_vbar), ("fold", fold)) if on]
+    return "+".join(parts) or "none"
 
 
 if __name__ == "__main__":

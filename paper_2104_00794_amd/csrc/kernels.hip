@@ -828,6 +828,324 @@ __global__ __launch_bounds__(256) void k_accum_full(const Layout L, const float 
     gpart[(int64_t)shot * L.nphys + pi.p] -= acc;
 }
 
+// ---------------------------------------------------------------------------
+// Probe contractions on the matrix cores.  A time block of b buffered levels
+// is the dense product acc (r x P) += Z^T (r x b) . F (b x P), F the buffered
+// field (or its second time difference) at P physical points.  The probes
+// of the counter-hash kinds are exact in bfloat16 (+-1, and multiples of 1/4
+// up to 8 in magnitude), and every FP32 field value splits exactly into
+// three bfloat16 parts (each keeps the next 8 significant bits), so three
+// bf16 products per tile accumulate, in FP32, the same terms as the FP32
+// contraction.  v_mfma_f32_16x16x16_bf16: lane l = 16 g + n supplies
+// A[m = n][k = 4 g + q] and B[k = 4 g + q][n], q = 0..3, and receives
+// D[m = 4 g + i][n], i = 0..3.  A wave covers 64 consecutive physical points
+// of one shot as four 16-point tiles; k runs over 16 buffered levels.
+// ---------------------------------------------------------------------------
+typedef short shortx4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int phys_offset(const Layout &L, int p) {
+    const int n0 = (int)L.n[0], n1 = (int)L.n[1];
+    const int row = p / n0, x = p - row * n0;
+    const int z = row / n1, y = row - z * n1;
+    const int oyb = L.ndim == 3 ? L.nb : 0;
+    return (int)L.pad_off(x + L.nb, y + oyb, z + L.nb);
+}
+
+// x = h + m + l exactly, each a bfloat16 (the upper 16 bits of a float)
+__device__ __forceinline__ void split_bf16x3(const float (&x)[4], shortx4 &h, shortx4 &m, shortx4 &l) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const unsigned uh = __float_as_uint(x[q]) & 0xffff0000u;
+        const float r1 = x[q] - __uint_as_float(uh);
+        const unsigned um = __float_as_uint(r1) & 0xffff0000u;
+        const float r2 = r1 - __uint_as_float(um);
+        h[q] = (short)(uh >> 16);
+        m[q] = (short)(um >> 16);
+        l[q] = (short)(__float_as_uint(r2) >> 16);
+    }
+}
+
+__device__ __forceinline__ floatx4 mfma_bf16x3(shortx4 a, shortx4 bh, shortx4 bm, shortx4 bl, floatx4 d) {
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bl, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bm, d, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, d, 0, 0, 0);
+}
+
+__device__ __forceinline__ int ring_slot(int s, int nslots) { return ((s % nslots) + nslots) % nslots; }
+
+// The buffered levels behind one 16-level group at this lane's four points:
+// f^{sb-1} .. f^{sb+4} (SD = 1) or f^{sb} .. f^{sb+3} (SD = 0), loaded one
+// group ahead of their use.  The loads are unconditional (every slot and
+// offset lies inside the ring) and the masks are applied at the use, so the
+// loads of the next group stay in flight while this group is contracted.
+template <int SD>
+struct GroupLoads {
+    float f[4][SD ? 6 : 4];
+};
+
+// sl: ring slot of level sb - SD (the first level loaded), kept incrementally
+// so the loop needs no division.
+template <int SD>
+__device__ __forceinline__ void group_load(const float *base, uint32_t slot_floats, int nslots, int sl,
+                                           const int (&off)[4], GroupLoads<SD> &G) {
+    constexpr int NE = SD ? 6 : 4;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const float *fs = base + (uint64_t)(uint32_t)sl * slot_floats;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) G.f[t][e] = fs[off[t]];
+        sl = sl + 1 == nslots ? 0 : sl + 1;
+    }
+}
+
+// The contracted values of levels sb..sb+3: f^s (SD = 0) or
+// f^{s-1} - 2 f^s + f^{s+1} (SD = 1) where s_lo <= s <= s_hi, else zero; a
+// buffered level outside s_lo - SD .. s_hi + SD, or a point past the end,
+// counts as zero (its slot may hold anything).
+template <int SD>
+__device__ __forceinline__ void group_values(const GroupLoads<SD> &G, int s_lo, int s_hi, int sb,
+                                             const bool (&ok)[4], float (&x)[4][4]) {
+#pragma clang fp contract(off)
+    constexpr int NE = SD ? 6 : 4;
+    float f[4][NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const int s = sb - SD + e;
+        const bool in = s >= s_lo - SD && s <= s_hi + SD;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) f[t][e] = (in && ok[t]) ? G.f[t][e] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bool in = sb + q >= s_lo && sb + q <= s_hi;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            x[t][q] = in ? (SD ? (f[t][q] - 2.0f * f[t][q + 1]) + f[t][q + 2] : f[t][q]) : 0.0f;
+    }
+}
+
+// Probe rows in the A-operand order: zpk[shot][kg][mt][lane] holds
+// Z[16 kg + 4 g + q][16 mt + n], q = 0..3, as four bfloat16 (zero past nt).
+__global__ __launch_bounds__(256) void k_pack_probes(int S, int nt, int r, const float *__restrict__ Z,
+                                                     uint2 *__restrict__ zpk) {
+    const int nkg = (nt + 15) / 16, nm = r / 16;
+    const int64_t total = (int64_t)S * nkg * nm * 64;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const int lane = (int)(idx & 63);
+    int64_t rest = idx >> 6;
+    const int mt = (int)(rest % nm);
+    rest /= nm;
+    const int kg = (int)(rest % nkg);
+    const int shot = (int)(rest / nkg);
+    const int g = lane >> 4, n = lane & 15;
+    unsigned v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int s = 16 * kg + 4 * g + q;
+        const float z = s < nt ? Z[((int64_t)shot * nt + s) * r + 16 * mt + n] : 0.0f;
+        v[q] = __float_as_uint(z) >> 16;
+    }
+    zpk[idx] = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+}
+
+// acc_j += sum_s Z[s, j] x^s for the RM x 16 probes j0 ..: ubar (forward) or
+// vbar (adjoint), x^s as in block_values.
+template <int RM, int SD>
+__global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float *__restrict__ ring, int nslots,
+                                                    int s_lo, int s_hi, const uint2 *__restrict__ zpk, int nkg,
+                                                    int r, int j0, float *__restrict__ out) {
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int shot = blockIdx.y;
+    int off[4], pidx[4];
+    bool ok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int p = (int)blockIdx.x * 256 + wave * 64 + 16 * t + n;
+        ok[t] = p < L.nphys;
+        pidx[t] = ok[t] ? p : 0;
+        off[t] = ok[t] ? phys_offset(L, p) : 0;
+    }
+    const float *base = ring + (int64_t)shot * L.shot_floats;
+    const int nm = r / 16;
+    const uint2 *zs = zpk + (int64_t)shot * nkg * nm * 64 + (j0 / 16) * 64 + lane;
+    floatx4 acc[RM][4];
+#pragma unroll
+    for (int mt = 0; mt < RM; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[mt][t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int kg_lo = s_lo >> 4, kg_hi = s_hi >> 4;
+    const int step16 = 16 % nslots;
+    int sl = ring_slot(16 * kg_lo + 4 * g - SD, nslots);
+    auto zload = [&](int kg, uint2 (&zz)[RM]) {
+#pragma unroll
+        for (int mt = 0; mt < RM; ++mt) zz[mt] = zs[((int64_t)kg * nm + mt) * 64];
+    };
+    auto contract = [&](const GroupLoads<SD> &G, const uint2 (&zz)[RM], int kg) {
+        float x[4][4];
+        group_values<SD>(G, s_lo, s_hi, 16 * kg + 4 * g, ok, x);
+        shortx4 bh[4], bm[4], bl[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) split_bf16x3(x[t], bh[t], bm[t], bl[t]);
+#pragma unroll
+        for (int mt = 0; mt < RM; ++mt) {
+            shortx4 a;
+            a[0] = (short)(zz[mt].x & 0xffffu);
+            a[1] = (short)(zz[mt].x >> 16);
+            a[2] = (short)(zz[mt].y & 0xffffu);
+            a[3] = (short)(zz[mt].y >> 16);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc[mt][t] = mfma_bf16x3(a, bh[t], bm[t], bl[t], acc[mt][t]);
+        }
+    };
+    // Software pipeline over two register sets: the loads of group kg + 1 are
+    // issued before group kg is contracted (the scheduling barrier keeps them
+    // there), so the wait for group kg leaves the next group's loads in
+    // flight.  The loop is unrolled twice so no set is copied.
+    GroupLoads<SD> ga, gb;
+    uint2 za[RM], zb[RM];
+    auto prefetch = [&](int kg, GroupLoads<SD> &G, uint2 (&zz)[RM]) {
+        sl += step16;
+        if (sl >= nslots) sl -= nslots;
+        group_load<SD>(base, (uint32_t)L.slot_floats, nslots, sl, off, G);
+        zload(kg, zz);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    group_load<SD>(base, (uint32_t)L.slot_floats, nslots, sl, off, ga);
+    zload(kg_lo, za);
+    int kg = kg_lo;
+    for (; kg + 2 <= kg_hi; kg += 2) {
+        prefetch(kg + 1, gb, zb);
+        contract(ga, za, kg);
+        prefetch(kg + 2, ga, za);
+        contract(gb, zb, kg + 1);
+    }
+    if (kg < kg_hi) {
+        prefetch(kg + 1, gb, zb);
+        contract(ga, za, kg);
+        contract(gb, zb, kg + 1);
+    } else {
+        contract(ga, za, kg);
+    }
+#pragma unroll
+    for (int mt = 0; mt < RM; ++mt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (!ok[t]) continue;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int j = j0 + 16 * mt + 4 * g + i;
+                out[((int64_t)shot * r + j) * L.nphys + pidx[t]] += acc[mt][t][i];
+            }
+        }
+}
+
+// gpart -= c sum_s x^s sum_j Z[s, j] ubar_j for the RK x 16 probes j0 ..:
+// per 16 levels, Y (16 levels x 16 points) = Z (levels x probes) . ubar
+// (probes x points) on the matrix cores, then the level sum against x^s in
+// FP32 and a fixed-order sum over the four lane groups.
+template <int RK, int SD>
+__global__ __launch_bounds__(256) void k_fold_mfma(const Layout L, const float *__restrict__ ring, int nslots,
+                                                   int s_lo, int s_hi, const float *__restrict__ Z, int nt, int r,
+                                                   int j0, const float *__restrict__ ubar, float c,
+                                                   float *__restrict__ gpart) {
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int g = lane >> 4, n = lane & 15;
+    const int shot = blockIdx.y;
+    int off[4], pidx[4];
+    bool ok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int p = (int)blockIdx.x * 256 + wave * 64 + 16 * t + n;
+        ok[t] = p < L.nphys;
+        pidx[t] = ok[t] ? p : 0;
+        off[t] = ok[t] ? phys_offset(L, p) : 0;
+    }
+    shortx4 uh[RK][4], um[RK][4], ul[RK][4];
+#pragma unroll
+    for (int kt = 0; kt < RK; ++kt)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int j = j0 + 16 * kt + 4 * g + q;
+                x[q] = ok[t] ? ubar[((int64_t)shot * r + j) * L.nphys + pidx[t]] : 0.0f;
+            }
+            split_bf16x3(x, uh[kt][t], um[kt][t], ul[kt][t]);
+        }
+    const float *base = ring + (int64_t)shot * L.shot_floats;
+    const float *Zs = Z + (int64_t)shot * nt * r + j0 + 4 * g;
+    float fsum[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const int kg_lo = s_lo >> 4, kg_hi = s_hi >> 4;
+    const int step16 = 16 % nslots;
+    int sl = ring_slot(16 * kg_lo + 4 * g - SD, nslots);
+    // probe rows of a group (A operands), loaded with the group's levels
+    auto zload = [&](int kg, float4 (&zv)[RK]) {
+        const int sa = 16 * kg + n;   // level of this lane's A row
+        const float *zr = Zs + (int64_t)(sa < nt ? sa : nt - 1) * r;
+#pragma unroll
+        for (int kt = 0; kt < RK; ++kt) zv[kt] = *(const float4 *)(zr + 16 * kt);
+    };
+    auto contract = [&](const GroupLoads<SD> &G, const float4 (&zv)[RK], int kg) {
+        const bool zin = 16 * kg + n < nt;
+        floatx4 d[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) d[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kt = 0; kt < RK; ++kt) {
+            shortx4 a;
+            a[0] = zin ? (short)(__float_as_uint(zv[kt].x) >> 16) : (short)0;
+            a[1] = zin ? (short)(__float_as_uint(zv[kt].y) >> 16) : (short)0;
+            a[2] = zin ? (short)(__float_as_uint(zv[kt].z) >> 16) : (short)0;
+            a[3] = zin ? (short)(__float_as_uint(zv[kt].w) >> 16) : (short)0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) d[t] = mfma_bf16x3(a, uh[kt][t], um[kt][t], ul[kt][t], d[t]);
+        }
+        float x[4][4];
+        group_values<SD>(G, s_lo, s_hi, 16 * kg + 4 * g, ok, x);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) fsum[t] = fmaf(x[t][i], d[t][i], fsum[t]);
+    };
+    // the same two-set software pipeline as the accumulation kernel
+    GroupLoads<SD> ga, gb;
+    float4 za[RK], zb[RK];
+    auto prefetch = [&](int kg, GroupLoads<SD> &G, float4 (&zz)[RK]) {
+        sl += step16;
+        if (sl >= nslots) sl -= nslots;
+        group_load<SD>(base, (uint32_t)L.slot_floats, nslots, sl, off, G);
+        zload(kg, zz);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    group_load<SD>(base, (uint32_t)L.slot_floats, nslots, sl, off, ga);
+    zload(kg_lo, za);
+    int kg = kg_lo;
+    for (; kg + 2 <= kg_hi; kg += 2) {
+        prefetch(kg + 1, gb, zb);
+        contract(ga, za, kg);
+        prefetch(kg + 2, ga, za);
+        contract(gb, zb, kg + 1);
+    }
+    if (kg < kg_hi) {
+        prefetch(kg + 1, gb, zb);
+        contract(ga, za, kg);
+        contract(gb, zb, kg + 1);
+    } else {
+        contract(ga, za, kg);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float v = fsum[t];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        if (g == 0 && ok[t]) gpart[(int64_t)shot * L.nphys + pidx[t]] -= c * v;
+    }
+}
+
 static dim3 point_grid(const Layout &L) {
     return dim3((unsigned)((L.nphys + 255) / 256), (unsigned)L.S);
 }
@@ -891,6 +1209,71 @@ hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int 
     else if (fold) launch_adj_chunks<1, 0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
     else if (sd) launch_adj_chunks<0, 1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
     else launch_adj_chunks<0, 0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, vbar, gpart);
+    return hipGetLastError();
+}
+
+size_t pack_probes_bytes(int S, int nt, int r) { return (size_t)S * ((nt + 15) / 16) * (r / 16) * 64 * 8; }
+
+hipError_t launch_pack_probes(int S, int nt, int r, const float *Z, void *zpk, hipStream_t stream) {
+    const int64_t total = (int64_t)S * ((nt + 15) / 16) * (r / 16) * 64;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_probes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, S, nt, r, Z,
+                       (uint2 *)zpk);
+    return hipGetLastError();
+}
+
+template <int SD>
+static void launch_accum_mfma_sd(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots,
+                                 int s_lo, int s_hi, const uint2 *zpk, int nkg, int r, float *out) {
+    for (int j0 = 0; j0 < r;) {
+        const int rm = std::min(4, (r - j0) / 16);
+#define TPX_MF(RM) hipLaunchKernelGGL((k_accum_mfma<RM, SD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, zpk, nkg, r, j0, out)
+        switch (rm) {
+        case 4: TPX_MF(4); break;
+        case 3: TPX_MF(3); break;
+        case 2: TPX_MF(2); break;
+        default: TPX_MF(1); break;
+        }
+#undef TPX_MF
+        j0 += 16 * rm;
+    }
+}
+
+hipError_t launch_accum_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const void *zpk,
+                             int nt, int r, int sd, float *out, hipStream_t stream) {
+    if (s_hi < s_lo) return hipSuccess;
+    if (r % 16 != 0 || s_lo < 0) return hipErrorInvalidValue;
+    const dim3 g = point_grid(L);
+    const int nkg = (nt + 15) / 16;
+    if (sd) launch_accum_mfma_sd<1>(L, g, stream, ring, nslots, s_lo, s_hi, (const uint2 *)zpk, nkg, r, out);
+    else launch_accum_mfma_sd<0>(L, g, stream, ring, nslots, s_lo, s_hi, (const uint2 *)zpk, nkg, r, out);
+    return hipGetLastError();
+}
+
+template <int SD>
+static void launch_fold_mfma_sd(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots, int s_lo,
+                                int s_hi, const float *Z, int nt, int r, const float *ubar, float c, float *gpart) {
+    for (int j0 = 0; j0 < r;) {
+        const int rk = std::min(4, (r - j0) / 16);
+#define TPX_FM(RK) hipLaunchKernelGGL((k_fold_mfma<RK, SD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar, c, gpart)
+        switch (rk) {
+        case 4: TPX_FM(4); break;
+        case 3: TPX_FM(3); break;
+        case 2: TPX_FM(2); break;
+        default: TPX_FM(1); break;
+        }
+#undef TPX_FM
+        j0 += 16 * rk;
+    }
+}
+
+hipError_t launch_fold_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z, int nt,
+                            int r, int sd, const float *ubar, float c, float *gpart, hipStream_t stream) {
+    if (s_hi < s_lo) return hipSuccess;
+    if (r % 16 != 0 || s_lo < 0) return hipErrorInvalidValue;
+    const dim3 g = point_grid(L);
+    if (sd) launch_fold_mfma_sd<1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
+    else launch_fold_mfma_sd<0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
     return hipGetLastError();
 }
 

@@ -405,6 +405,11 @@ tpx_status build_tables(const Problem &P, const tpx_grid *g, const tpx_geom *geo
 // Library options (tpx_set_option).  Overlap: probe contractions run on an
 // auxiliary stream, concurrently with the next block of time steps.
 std::atomic<int> g_overlap{0};
+// Matrix-core contractions: 0 never; 1 (default) where they were measured
+// faster: the folded adjoint contraction for r >= 32, the accumulations of
+// ubar and vbar for r >= 64; 2 every contraction whenever the probes qualify
+// (a kind exact in bfloat16 and r a multiple of 16).
+std::atomic<int> g_mfma{1};
 
 // Auxiliary streams, created on first use and kept for the process lifetime.
 std::mutex g_aux_mu;
@@ -442,12 +447,27 @@ int default_block(const Layout &L, int nt, bool overlap) {
 }
 
 struct Plan {
-    size_t flags, parts, J, beta, ring, hist, Z, rfW, rfY, ubar, vbar, gpart, res, d, tables, total;
+    size_t flags, parts, J, beta, ring, hist, Z, zpk, rfW, rfY, ubar, vbar, gpart, res, d, tables, total;
     int nslots, block;
     bool overlap;
 };
 
 enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED, M_RANGE_FINDER, M_OBJECTIVE };
+
+// Probes whose entries are exact in bfloat16 (counter-hash kinds) and whose
+// count is a multiple of 16 can be contracted on the matrix cores.
+bool mfma_eligible(const tpx_probe *pr) {
+    return pr && (pr->kind == TPX_PROBE_RADEMACHER || pr->kind == TPX_PROBE_GAUSS_B64) && pr->r % 16 == 0;
+}
+
+enum { MFMA_ACCUM = 1, MFMA_FOLD = 2 };
+
+int mfma_selected(const tpx_probe *pr) {
+    const int opt = g_mfma.load();
+    if (!mfma_eligible(pr) || opt == 0) return 0;
+    if (opt == 2) return MFMA_ACCUM | MFMA_FOLD;
+    return (pr->r >= 64 ? MFMA_ACCUM : 0) | (pr->r >= 32 ? MFMA_FOLD : 0);
+}
 
 tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     if (!pr) return fail(TPX_E_INVAL, "probe must not be NULL for probed calls");
@@ -500,6 +520,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     p.ring = take(slot * p.nslots);
     if (mode == M_GRAD_FULL) p.hist = take(slot * (size_t)P.nt);
     if (probed && pr->kind != TPX_PROBE_EXPLICIT) p.Z = take((size_t)L.S * P.nt * r * 4);
+    if (probed && mfma_eligible(pr)) p.zpk = take(pack_probes_bytes(L.S, P.nt, r));
     if (probed && pr->kind == TPX_PROBE_RANGE_FINDER) {
         p.rfW = take((size_t)L.S * P.nrec * pr->r * 8);
         p.rfY = take((size_t)L.S * P.nt * pr->r * 8);
@@ -531,6 +552,8 @@ struct Ctx {
     SampleTables rec_smp, src_smp;  // out/scales filled per use
     float *beta = nullptr;
     float *ring = nullptr;
+    const void *zpk = nullptr;   // packed probes when the accumulations run on the matrix cores
+    bool fold_mfma = false;      // the folded adjoint contraction runs on the matrix cores
     // overlap of the contractions: auxiliary stream and per-block events
     // (block i uses slot i & 1; the main stream waits for block i's
     // contraction before block i + 2 starts overwriting its ring slots)
@@ -799,6 +822,9 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
             // levels s_lo..s_hi are new: contract them (dtt 0), or the second
             // differences centred at k = s_lo-1..s_hi-1, which they complete (dtt 1)
             auto contract = [&](hipStream_t cs) {
+                if (C.zpk)
+                    return f.dtt ? launch_accum_mfma(L, f.buf, f.ns, s_lo - 1, s_hi - 1, C.zpk, nt, f.r, 1, f.ubar, cs)
+                                 : launch_accum_mfma(L, f.buf, f.ns, s_lo, s_hi, C.zpk, nt, f.r, 0, f.ubar, cs);
                 return f.dtt ? launch_accum_adj(L, f.buf, f.ns, s_lo - 1, s_hi - 1, f.Z, nt, f.r, 0, 1, nullptr, 1.0f,
                                                 f.ubar, nullptr, cs)
                              : launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, cs);
@@ -939,9 +965,13 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
             const int lo = o.dtt && k_last == 1 ? 0 : k_last;
             const int hi = o.dtt ? std::min(s_hi, nt - 2) : s_hi;
             auto contract = [&] {
-                return o.hist ? launch_accum_full(L, o.hist, C.ring, ns, k_last, s_hi, o.gpart, cs)
-                              : launch_accum_adj(L, C.ring, ns, lo, hi, o.Z, nt, o.r, o.fold, o.dtt ? 0 : 1, o.ubar,
-                                                 o.c, o.vbar, o.gpart, cs);
+                if (o.hist) return launch_accum_full(L, o.hist, C.ring, ns, k_last, s_hi, o.gpart, cs);
+                const int sd = o.dtt ? 0 : 1;
+                if (o.fold && C.fold_mfma)
+                    return launch_fold_mfma(L, C.ring, ns, lo, hi, o.Z, nt, o.r, sd, o.ubar, o.c, o.gpart, cs);
+                if (!o.fold && C.zpk) return launch_accum_mfma(L, C.ring, ns, lo, hi, C.zpk, nt, o.r, sd, o.vbar, cs);
+                return launch_accum_adj(L, C.ring, ns, lo, hi, o.Z, nt, o.r, o.fold, sd, o.ubar, o.c, o.vbar,
+                                        o.gpart, cs);
             };
             const int kind = o.hist ? TPX_KERNEL_ACCUM_FULL : TPX_KERNEL_ACCUM_ADJ;
             if (ovl) {
@@ -994,6 +1024,13 @@ const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, const float *d_obs, t
             return launch_range_finder(C.P.L.S, C.P.nt, C.P.nrec, pr->r, d_obs, Z, (double *)(C.ws + C.plan.rfW),
                                        (double *)(C.ws + C.plan.rfY), C.stream);
         });
+    const int mm = mfma_selected(pr);
+    if (e == hipSuccess && (mm & MFMA_ACCUM)) {
+        void *zpk = C.ws + C.plan.zpk;
+        e = prof(KIND_OTHER, C.stream, [&] { return launch_pack_probes(C.P.L.S, C.P.nt, pr->r, Z, zpk, C.stream); });
+        C.zpk = zpk;
+    }
+    C.fold_mfma = (mm & MFMA_FOLD) != 0;
     if (e != hipSuccess) *st = fail(TPX_E_DEVICE, std::string("probe generation: ") + hipGetErrorString(e));
     return Z;
 }
@@ -1376,11 +1413,17 @@ tpx_status tpx_set_option(int32_t option, int64_t value) {
         g_overlap.store(value ? 1 : 0);
         return TPX_OK;
     }
+    if (option == TPX_OPT_MATRIX_CORES) {
+        if (value < 0 || value > 2) return fail(TPX_E_INVAL, "TPX_OPT_MATRIX_CORES takes 0, 1 or 2");
+        g_mfma.store((int)value);
+        return TPX_OK;
+    }
     return fail(TPX_E_INVAL, "unknown option");
 }
 
 int64_t tpx_get_option(int32_t option) {
     if (option == TPX_OPT_OVERLAP_CONTRACTIONS) return g_overlap.load();
+    if (option == TPX_OPT_MATRIX_CORES) return g_mfma.load();
     return -1;
 }
 

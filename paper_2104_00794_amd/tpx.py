@@ -443,6 +443,7 @@ class Job:
 
 KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL, KERNEL_STEP2 = range(5)
 OPT_OVERLAP_CONTRACTIONS = 1
+OPT_MATRIX_CORES = 2
 
 
 def set_option(option: int, value: int):
