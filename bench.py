@@ -238,7 +238,8 @@ def serving(args, dev):
         grid = tpx.Grid(wl.shape, h=wl.h, dt=wl.dt, nt=wl.nt, order=wl.order, nbl=wl.nbl, damp_vmax=wl.vmax)
         geom = tpx.Geometry(wl.src_pos(), wl.rec_pos(), torch.tensor(wl.wavelet(), dtype=torch.float32, device=dev))
         d_obs = tpx.forward(grid, geom, torch.tensor(mt, dtype=torch.float32, device=dev))
-        reqs.append(serve.Request(i, grid, geom, tpx.Probe(r=wl.r, seed=wl.probe_seed),
+        # a 256-level ring per request keeps many jobs inside the server's budget
+        reqs.append(serve.Request(i, grid, geom, tpx.Probe(r=wl.r, seed=wl.probe_seed, block=256),
                                   torch.tensor(m0, dtype=torch.float32, device=dev), d_obs))
     torch.cuda.synchronize()
     # service time of the plain path (also the warm-up), then the arrival rate
@@ -297,6 +298,7 @@ def cpu_baseline(wl, r, kind, nt_sample, shots, d_obs):
 
 def matrix_core_use(kind: str, r: int, keep_vbar: bool) -> str:
     """Which contractions run on the matrix cores under the library option."""
+    from paper_2104_00794_amd import tpx
     opt = tpx.get_option(tpx.OPT_MATRIX_CORES)
     if kind not in ("rademacher", "gauss_b64") or r % 16 != 0 or opt == 0:
         return "none"

@@ -435,11 +435,15 @@ void aux_release(hipStream_t s) {
 int ring_slots(int b, bool overlap) { return overlap ? 2 * b + 3 : b + 2; }
 
 // Time steps buffered per probe contraction: the accumulators' read-modify-
-// write costs 8 r / b bytes per point-step, the ring costs ring_slots(b) slots.
-int default_block(const Layout &L, int nt, bool overlap) {
+// write costs 8 r / b bytes per point-step against the 4 bytes of the ring
+// read, and the ring costs ring_slots(b) slots.  b starts at 16 r (the
+// accumulator traffic at an eighth of the ring's), within 256 .. 1024, and is
+// halved while the ring exceeds 80 GB (under 30% of the GPU's 288 GB).
+int default_block(const Layout &L, int nt, bool overlap, int r) {
     const double slot_bytes = (double)L.slot_floats * 4.0;
-    const double cap = 48e9;
+    const double cap = 80e9;
     int b = 256;
+    while (b < 1024 && b < 16 * r) b *= 2;
     while (b > 16 && ring_slots(b, overlap) * slot_bytes > cap) b /= 2;
     if (b > nt - 1) b = nt - 1;
     if (b < 1) b = 1;
@@ -498,7 +502,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     const int r = probed ? pr->r : 0;
     const bool plain = mode == M_FORWARD || mode == M_ADJOINT || mode == M_OBJECTIVE;
     p.overlap = g_overlap.load() != 0 && !plain;
-    p.block = default_block(L, P.nt, p.overlap);
+    p.block = default_block(L, P.nt, p.overlap, r);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
     // without contractions the ring holds the levels one launch touches: three,

@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the measurement records under ``profiles/``.
 
-Two kinds of summary are written, both short markdown text:
+Three kinds of summary are written, all short markdown text:
 
 * kernel statistics of one run (``rocprofv3 --kernel-trace --stats``): calls,
   total and average duration per kernel;
@@ -8,11 +8,14 @@ Two kinds of summary are written, both short markdown text:
   counters (two separate ``--pmc`` runs), each scaled by the factor that makes
   the same counter report the known size of a plain device copy.  The summary
   records the SHA-256 of the kernel source it was measured with; ``bench.py``
-  reports the traffic only while that source is unchanged.
+  reports the traffic only while that source is unchanged;
+* other hardware counters of chosen kernels (``--pmc`` runs), mean per dispatch.
 
 Usage (from the repository root)::
 
     python -m paper_2104_00794_amd.profiling kernels DB OUT --title T --cmd C
+    python -m paper_2104_00794_amd.profiling counters OUT --db DB [--db DB ...] --kernel K [--kernel K ...] \\
+        --title T --cmd C [--cmd C ...]
     python -m paper_2104_00794_amd.profiling traffic OUT --kernel K --workload W \\
         --fetch-db DB --write-db DB --copy-fetch-db DB --copy-write-db DB \\
         --copy-bytes N --alg-bytes N --cmd C [--cmd C ...]
@@ -114,6 +117,45 @@ def write_traffic_summary(out: str, kernel: str, workload: str, fetch_db: str, w
     return text
 
 
+def counter_table(db: str):
+    """{(kernel name, counter): (mean per dispatch, dispatches)} of one --pmc run."""
+    con = sqlite3.connect(_db(db))
+    acc = {}
+    for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
+        tot, n = acc.get((k, c), (0.0, 0))
+        acc[(k, c)] = (tot + v, n + 1)
+    con.close()
+    return {key: (tot / n, n) for key, (tot, n) in acc.items()}
+
+
+def write_counter_summary(dbs, out: str, title: str, kernels, cmds, notes=()) -> str:
+    """Mean per-dispatch values of every counter in the --pmc runs `dbs`, for
+    the kernels whose names contain one of `kernels`."""
+    rows = {}
+    counters = []
+    for db in dbs:
+        for (k, c), (mean, n) in counter_table(db).items():
+            tag = next((t for t in kernels if t in k), None)
+            if tag is None:
+                continue
+            rows.setdefault(tag, {})[c] = (mean, n)
+            if c not in counters:
+                counters.append(c)
+    lines = ["# %s" % title, "", "Commands (repository root, one MI355X; each counter set in its own run):", "",
+             "```", *cmds, "```", "", "Mean value per dispatch (dispatch count in parentheses).", "",
+             "| kernel | " + " | ".join(counters) + " |", "|---" * (len(counters) + 1) + "|"]
+    for tag in kernels:
+        if tag not in rows:
+            continue
+        cells = ["%.4g (%d)" % rows[tag][c] if c in rows[tag] else "" for c in counters]
+        lines.append("| `%s` | " % tag + " | ".join(cells) + " |")
+    lines += [""] + list(notes)
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    return text
+
+
 def traffic_path(workload: str, kernel_tag: str) -> str:
     return os.path.join(PROFILES, "%s_%s_traffic.md" % (kernel_tag, workload))
 
@@ -146,9 +188,18 @@ def main(argv=None) -> None:
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--alg-bytes", type=float, required=True)
     t.add_argument("--cmd", action="append", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("--db", action="append", required=True)
+    c.add_argument("--kernel", action="append", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--cmd", action="append", required=True)
+    c.add_argument("--note", action="append", default=[])
     a = ap.parse_args(argv)
     if a.what == "kernels":
         print(write_kernel_summary(a.db, a.out, a.title, a.cmd))
+    elif a.what == "counters":
+        print(write_counter_summary(a.db, a.out, a.title, a.kernel, a.cmd, a.note))
     else:
         print(write_traffic_summary(a.out, a.kernel, a.workload, a.fetch_db, a.write_db, a.copy_fetch_db,
                                     a.copy_write_db, a.copy_bytes, a.alg_bytes, a.cmd))

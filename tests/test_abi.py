@@ -86,7 +86,7 @@ def test_full_history_of_3d_config_exceeds_one_gpu():
     full = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom)
     probed = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=32))
     assert full > 288e9
-    assert probed < 0.25 * 288e9
+    assert probed < 0.35 * 288e9   # a 256-level ring (78 GB) and the accumulators
 
 
 def test_probe_side_validated():
