@@ -409,19 +409,28 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
     const float hxy_a = FAST ? 0.0f : hx + layer_frac2(ya, (int)L.n[1], L.nb, ph.inv_nb);
     const float hxy_b = FAST ? 0.0f : hx + layer_frac2(yb, (int)L.n[1], L.nb, ph.inv_nb);
 
+    // the column's own loads of a plane: u^k at z + R, u^{k-1} and beta at z;
+    // issued one plane ahead, like the halo, so they overlap a plane of compute
+    float nq[2], np[2], nbt[2];
+    auto load_column = [&](int z) {
+        const uint32_t zo = plane(z), zr_o = plane(z + R);
+        nq[0] = buf_load(rc, va, zr_o);
+        nq[1] = buf_load(rc, vb, zr_o);
+        np[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)va, (int)zo, kBufNT));
+        np[1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)vb, (int)zo, kBufNT));
+        nbt[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)va, (int)zo, kBufNT));
+        nbt[1] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)vb, (int)zo, kBufNT));
+    };
+    load_column(zc0);
+
     for (int lz = 0; lz < T3Z; ++lz) {
         const int z = zc0 + lz;
         if (!FAST && z >= P2) break;
-        const uint32_t zo = plane(z), zr_o = plane(z + R);
+        const uint32_t zo = plane(z);
         const bool zr = FAST || z + R < P2;
-        const float qa_ = buf_load(rc, va, zr_o), qb_ = buf_load(rc, vb, zr_o);
-        qa[2 * R] = (oa && zr) ? qa_ : 0.0f;
-        qb[2 * R] = (ob && zr) ? qb_ : 0.0f;
-        const float pa_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)va, (int)zo, kBufNT));
-        const float pb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)vb, (int)zo, kBufNT));
-        const float ba_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)va, (int)zo, kBufNT));
-        const float bb_ = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)vb, (int)zo, kBufNT));
-        const float pa = oa ? pa_ : 0.0f, pb = ob ? pb_ : 0.0f, ba = oa ? ba_ : 0.0f, bb = ob ? bb_ : 0.0f;
+        qa[2 * R] = (oa && zr) ? nq[0] : 0.0f;
+        qb[2 * R] = (ob && zr) ? nq[1] : 0.0f;
+        const float pa = oa ? np[0] : 0.0f, pb = ob ? np[1] : 0.0f, ba = oa ? nbt[0] : 0.0f, bb = ob ? nbt[1] : 0.0f;
 
         float(*pt)[W] = plane_t[lz & 1];
         pt[ly][lx] = h[0];
@@ -447,7 +456,10 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
             }
         }
         __syncthreads();
-        if (lz + 1 < T3Z && (FAST || z + 1 < P2)) load_halo(z + 1, h);   // prefetch, overlaps the compute below
+        if (lz + 1 < T3Z && (FAST || z + 1 < P2)) {   // prefetch, overlaps the compute below
+            load_halo(z + 1, h);
+            load_column(z + 1);
+        }
 
         float lapa = 3.0f * ph.c[0] * qa[R], lapb = 3.0f * ph.c[0] * qb[R];
 #pragma unroll
@@ -479,7 +491,7 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
 }
 
 template <int R>
-__global__ __launch_bounds__(256) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
     __shared__ float plane_t[2][T3Y + 2 * R][T3X + 2 * R];
     const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
     const int nzc = (int)((L.P[2] + T3Z - 1) / T3Z);
