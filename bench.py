@@ -55,6 +55,10 @@ def parse():
                     help="serving mix instead: continuous batching vs one-at-a-time on one Poisson trace")
     ap.add_argument("--requests", type=int, default=60, help="requests in the serving trace")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget of the server")
+    ap.add_argument("--chunk-steps", type=int, default=128, help="time steps a served job advances per turn")
+    ap.add_argument("--max-active", type=int, default=4,
+                    help="jobs the server keeps on the GPU at once (default: one per hardware queue)")
+    ap.add_argument("--inflight", type=int, default=2, help="chunks each served job keeps queued")
     return ap.parse_args()
 
 
@@ -250,10 +254,20 @@ def serving(args, dev):
     for q, a in zip(reqs, arr):
         q.arrival = float(a)
     seq = serve.run_sequential(reqs)
-    srv = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=128, max_active=16, nstreams=8)
+    srv = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=args.chunk_steps,
+                       max_active=args.max_active, nstreams=8, inflight=args.inflight)
     bat = srv.run(reqs)
     same = all(torch.equal(seq[q.rid].g, bat[q.rid].g) for q in reqs if bat[q.rid].status == "ok")
     a, b = serve.summarize(seq, reqs), serve.summarize(bat, reqs)
+    # saturation: every request queued at once, so the makespan measures how
+    # much work the GPU absorbs when jobs overlap (small grids alone leave most
+    # of the 256 CUs idle)
+    for q in reqs:
+        q.arrival = 0.0
+    sat_seq = serve.summarize(serve.run_sequential(reqs), reqs)
+    srv2 = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=args.chunk_steps,
+                        max_active=args.max_active, nstreams=8, inflight=args.inflight)
+    sat_bat = serve.summarize(srv2.run(reqs), reqs)
     out = {
         "metric": "serving: gradient p50/p99 latency and aggregate GPts/s, continuous batching vs one-at-a-time",
         "value": b["gpts_per_s"], "unit": "GPts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
@@ -261,8 +275,11 @@ def serving(args, dev):
         "config": {"workload": "serving mix: 2D 201x201..1001x401 (1-32 shots), 3D 201^3 (1 shot), "
                                "r in {8,32,64}, order 8", "requests": len(reqs),
                    "arrival": "Poisson, %.2f req/s = 0.8 x sequential service rate" % rate,
-                   "hbm_budget_gb": args.budget_gb, "chunk_steps": 128},
+                   "hbm_budget_gb": args.budget_gb, "chunk_steps": args.chunk_steps,
+                   "max_active": args.max_active, "inflight": args.inflight},
         "batched": b, "sequential": a, "mean_service_ms": round(1e3 * mean_service, 2),
+        "saturated": {"batched": sat_bat, "sequential": sat_seq,
+                      "throughput_ratio": round(sat_bat["gpts_per_s"] / sat_seq["gpts_per_s"], 3)},
         "peak_active_jobs": srv.peak_active, "peak_workspace_gb": round(srv.peak_bytes / 1e9, 2),
         "results_identical": bool(same),
     }

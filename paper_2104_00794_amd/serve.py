@@ -67,7 +67,12 @@ class _Active:
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 128, max_active: int = 16,
+    """max_active defaults to 4, the number of hardware queues HIP gives a
+    process here (GPU_MAX_HW_QUEUES): more concurrent jobs share queues and
+    caches, and the measured saturated throughput drops below the sequential
+    path's."""
+
+    def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 128, max_active: int = 4,
                  nstreams: int = 8, inflight: int = 2, device=None):
         self.budget = float(hbm_budget_bytes)
         self.chunk = int(chunk_steps)

@@ -116,3 +116,23 @@ def test_probed_inversion_reduces_the_model_error():
         assert all(h.t > 0.0 for h in res.history)
         # the box, as its bounds round to the model's float32
         assert float(res.x.min()) >= float(np.float32(prob.lo)) and float(res.x.max()) <= float(np.float32(prob.hi))
+
+
+def test_objective_edge_cases():
+    import torch
+    _print_case("objective_edges")
+    c = Case(small_2d(nz=30, nx=40, nt=60, nshots=2, nrec=5, order=4))
+    m = cuda(c.m0)
+    # no receivers: nothing to misfit
+    geom0 = tpx.Geometry(c.src, np.zeros((2, 0, 3)), cuda(c.wav))
+    J0 = tpx.objective(c.tgrid(), geom0, m, torch.zeros((2, c.wl.nt, 0), device="cuda"))
+    assert float(J0.item()) == 0.0
+    # the observed data equal to the model's own traces: zero misfit, bitwise
+    d = tpx.forward(c.tgrid(), c.tgeom(), m)
+    assert float(tpx.objective(c.tgrid(), c.tgeom(), m, d).item()) == 0.0
+    # the shortest record, two time levels
+    c2 = Case(small_2d(nz=30, nx=40, nt=2, nshots=1, nrec=3, order=8))
+    dob = np.ones((1, 2, 3))
+    J2 = tpx.objective(c2.tgrid(), c2.tgeom(), cuda(c2.m0), cuda(dob))
+    J2o = _oracle_J(c2, c2.m0, np.arange(1), dob)
+    assert abs(float(J2.item()) - J2o) <= TOL * J2o
