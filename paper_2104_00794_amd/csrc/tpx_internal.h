@@ -32,7 +32,7 @@ __host__ __device__ constexpr int t2x(int R) { return 64 - 2 * R; }
 // 3D step kernel tile: 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
 constexpr int T3Y = 8;
-constexpr int T3Z = 32;
+constexpr int T3Z = 12;
 
 struct Layout {
     int ndim;      // 2 or 3

@@ -3,7 +3,7 @@ inputs.  Bars: probes bit-exact; traces, adjoint outputs and gradients within
 relative L2 <= 1e-4 (FP32 on the GPU vs FP64 in the oracle).
 
 Sizes span several step-kernel tiles (64 x 16 in 2D, 64 x 8 columns with
-32-plane z chunks in 3D) with ragged edges, both stencil orders, several
+12-plane z chunks in 3D) with ragged edges, both stencil orders, several
 shots, off-grid and on-grid sources/receivers, and the edge cases nt = 2,
 no receivers, receivers on the last grid line.
 """
@@ -237,10 +237,10 @@ def test_c0_two_layer_full_and_probed():
 
 
 def test_3d_sources_across_z_chunk_boundary_and_dense_receivers():
-    # receivers straddle the boundary between the first two 32-plane z chunks
-    # (padded z = 31.5) and sit 0.37 h apart, so several share injection nodes
+    # receivers straddle the boundary between the second and third 12-plane z
+    # chunks (padded z = 23.5) and sit 0.37 h apart, so several share injection nodes
     wl = small_3d(nz=48, ny=12, nx=40, nt=80, nbl=5, nshots=2, nrec=4)
-    zc = (32 - wl.nbl - 0.5) * wl.h
+    zc = (24 - wl.nbl - 0.5) * wl.h
     rec = [(3.0 + 0.37 * wl.h * i, 0.5 * (wl.shape[1] - 1) * wl.h, zc) for i in range(30)]
     wl = wl.with_(rec=rec)
     _print_case("3d_chunk_boundary")
