@@ -66,7 +66,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the whole gradient of a shot batch on a single "
+        print("bench.py measures one GPU: the library runs the whole gradient of a shot batch on a single "
               "MI355X and has no multi-GPU path (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
               file=sys.stderr)
         sys.exit(2)

@@ -1,0 +1,38 @@
+"""CPU tests of bench.py's host logic: one GPU only, and the record of which
+contractions run on the matrix cores."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_before_any_device_work():
+    env = dict(os.environ, HIP_VISIBLE_DEVICES="")
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=120)
+    assert p.returncode != 0
+    assert "one" in (p.stdout + p.stderr).lower() and "--gpus 2" in (p.stdout + p.stderr)
+
+
+def test_matrix_core_record_follows_the_library_option():
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2104_00794_amd import tpx
+    from tests.helpers import ensure_built
+    ensure_built()
+    old = tpx.get_option(tpx.OPT_MATRIX_CORES)
+    try:
+        tpx.set_option(tpx.OPT_MATRIX_CORES, 1)
+        assert bench.matrix_core_use("rademacher", 16, False) == "none"
+        assert bench.matrix_core_use("rademacher", 32, False) == "fold"
+        assert bench.matrix_core_use("rademacher", 64, False) == "ubar+fold"
+        assert bench.matrix_core_use("gauss_b64", 64, True) == "ubar+vbar"
+        assert bench.matrix_core_use("range_finder", 64, False) == "none"
+        assert bench.matrix_core_use("rademacher", 40, False) == "none"
+        tpx.set_option(tpx.OPT_MATRIX_CORES, 2)
+        assert bench.matrix_core_use("rademacher", 16, True) == "ubar+vbar"
+        tpx.set_option(tpx.OPT_MATRIX_CORES, 0)
+        assert bench.matrix_core_use("rademacher", 64, False) == "none"
+    finally:
+        tpx.set_option(tpx.OPT_MATRIX_CORES, old)
