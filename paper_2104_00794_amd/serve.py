@@ -9,6 +9,10 @@ several jobs overlaps on the device; requests that arrive while others run
 join at the next chunk boundary.  A job's results do not depend on its
 neighbours (separate workspaces, deterministic kernels).
 
+A request may be withdrawn (``Request.cancel_at``): waiting, it leaves the
+queue; running, it stops advancing and its workspace is freed as soon as the
+chunks already queued on its stream have run, without touching the others.
+
 ``run_sequential`` is the plain path: one ``tpx_gradient_probed`` call at a
 time in arrival order, on the same arrival trace.
 """
@@ -34,6 +38,7 @@ class Request:
     m: torch.Tensor
     d_obs: torch.Tensor
     arrival: float = 0.0          # seconds after the start of the run
+    cancel_at: Optional[float] = None   # the client withdraws the request at this time (seconds)
 
     @property
     def updates(self) -> int:
@@ -64,6 +69,7 @@ class _Active:
     def __init__(self, req: Request, job: tpx.Job, stream, need: int, admitted: float):
         self.req, self.job, self.stream, self.need, self.admitted = req, job, stream, need, admitted
         self.events = collections.deque()
+        self.cancelled = False
 
 
 class Server:
@@ -82,6 +88,7 @@ class Server:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nstreams)]
         self.peak_active = 0
         self.peak_bytes = 0
+        self.in_use_bytes = 0   # workspace bytes still held when run() returns
 
     def run(self, requests: List[Request]) -> Dict[int, Result]:
         reqs = sorted(requests, key=lambda r: r.arrival)
@@ -98,6 +105,16 @@ class Server:
                 r = pend.popleft()
                 results[r.rid] = Result(r.rid, r.arrival)
                 waiting.append(r)
+            # withdrawn requests: a waiting one leaves the queue; an active one
+            # stops advancing and frees its workspace once its queued chunks ran
+            for r in [q for q in waiting if q.cancel_at is not None and q.cancel_at <= now]:
+                waiting.remove(r)
+                results[r.rid].status = "cancelled"
+                results[r.rid].finished = now
+            for st in active:
+                if not st.cancelled and st.req.cancel_at is not None and st.req.cancel_at <= now:
+                    st.cancelled = True
+                    results[st.req.rid].status = "cancelled"
             # admission at chunk boundaries, first come first served
             while waiting and len(active) < self.max_active and free_streams:
                 req = waiting[0]
@@ -123,11 +140,12 @@ class Server:
             for st in list(active):
                 while st.events and st.events[0].query():
                     st.events.popleft()
-                if st.job.finished:
+                if st.job.finished or st.cancelled:
                     if not st.events:
                         res = results[st.req.rid]
                         res.finished = time.perf_counter() - t0
-                        res.g, res.J = st.job.g, st.job.J
+                        if not st.cancelled:
+                            res.g, res.J = st.job.g, st.job.J
                         st.job.close()
                         st.job.ws = None
                         active.remove(st)
@@ -144,6 +162,7 @@ class Server:
             if not active and not waiting and pend:
                 time.sleep(max(0.0, min(pend[0].arrival - (time.perf_counter() - t0), 0.001)))
         torch.cuda.synchronize(self.device)
+        self.in_use_bytes = used
         return results
 
 
@@ -169,11 +188,13 @@ def run_sequential(requests: List[Request], device=None) -> Dict[int, Result]:
 
 def summarize(results: Dict[int, Result], requests: List[Request]) -> dict:
     ok = [r for r in results.values() if r.status == "ok"]
+    cancelled = sum(1 for r in results.values() if r.status == "cancelled")
     lat = np.array([r.latency for r in ok]) * 1e3
     start = min(r.arrival for r in results.values())
     end = max(r.finished for r in ok)
     upd = sum(q.updates for q in requests if results[q.rid].status == "ok")
-    return {"requests": len(results), "completed": len(ok), "rejected": len(results) - len(ok),
+    return {"requests": len(results), "completed": len(ok), "cancelled": cancelled,
+            "rejected": len(results) - len(ok) - cancelled,
             "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "mean_ms": round(float(lat.mean()), 2), "makespan_s": round(end - start, 3),
             "gpts_per_s": round(upd / (end - start) / 1e9, 2)}

@@ -68,3 +68,22 @@ def test_admission_by_hbm_budget():
     tiny = serve.Server(hbm_budget_bytes=min(need) / 2, chunk_steps=64)
     res = tiny.run(reqs[:2])
     assert all(r.status.startswith("rejected") for r in res.values())
+
+
+def test_cancellation_frees_the_workspace_and_leaves_the_others_unchanged():
+    reqs = [make_request(i, arrival=0.0) for i in range(6)]
+    alone = serve.run_sequential(reqs)
+    reqs[1].cancel_at = 0.0          # withdrawn before it can start
+    reqs[2].cancel_at = 0.01         # withdrawn while running (or waiting)
+    srv = serve.Server(hbm_budget_bytes=50e9, chunk_steps=16, max_active=3, nstreams=4)
+    res = srv.run(reqs)
+    assert res[1].status == "cancelled" and res[1].g is None
+    assert res[2].status in ("cancelled", "ok")
+    assert srv.in_use_bytes == 0
+    for r in reqs:
+        if r.rid in (1, 2):
+            continue
+        assert res[r.rid].status == "ok"
+        assert torch.equal(res[r.rid].g, alone[r.rid].g) and torch.equal(res[r.rid].J, alone[r.rid].J)
+    s = serve.summarize(res, reqs)
+    assert s["cancelled"] >= 1 and s["completed"] + s["cancelled"] == len(reqs)
