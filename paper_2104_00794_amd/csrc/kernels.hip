@@ -1533,14 +1533,14 @@ __global__ __launch_bounds__(1024) void k_rf_qr(int nt, int r, double *__restric
         }
         __syncthreads();
     };
-    // A[t][k] -= tau v_t w_k for t >= j, k in (kmin, r)
+    // A[t][k] -= tau v_t w_k for t >= j, k in (kmin, r): thread (tx, ty) owns
+    // column tx and every 16th row (column j, read here, is not written)
     auto apply = [&](int j, int kmin, double tj) {
-        const int64_t n = (int64_t)(nt - j) * r;
-        for (int64_t idx = tid; idx < n; idx += 1024) {
-            const int t = j + (int)(idx / r), k = (int)(idx % r);
-            if (k > kmin) {
+        if (tx > kmin && tx < r) {
+            const double wk = wv[tx];
+            for (int t = j + ty; t < nt; t += 16) {
                 const double vt = t == j ? 1.0 : A[(int64_t)t * r + j];
-                A[(int64_t)t * r + k] -= tj * vt * wv[k];
+                A[(int64_t)t * r + tx] -= tj * vt * wk;
             }
         }
         __syncthreads();
