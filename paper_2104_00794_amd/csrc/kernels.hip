@@ -5,6 +5,8 @@
 // floating-point atomics.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "tpx_internal.h"
 
 namespace tpx {
@@ -1438,27 +1440,47 @@ hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_
 // shot's Rademacher probes.  FP64 throughout, fixed summation orders.
 // ---------------------------------------------------------------------------
 
-// W[s][i][j0 + c] = sum_t D[s][t][i] Z[s][t][j0 + c], c < RC: one thread per receiver.
+// The D^T Z product is split over kRfSeg time segments, so the launch has
+// receivers/64 x shots x kRfSeg blocks; the segments are then summed in order.
+constexpr int kRfSeg = 16;
+
+// P[s][seg][i][c] = sum over the segment's samples t of D[s][t][i] Z[s][t][j0 + c].
 template <int RC>
-__global__ __launch_bounds__(256) void k_rf_dtz(int nt, int nrec, int r, int j0, const float *__restrict__ D,
-                                                const float *__restrict__ Z, double *__restrict__ W) {
-    const int s = blockIdx.y;
-    const int i = (int)blockIdx.x * 256 + (int)threadIdx.x;
+__global__ __launch_bounds__(64) void k_rf_dtz(int nt, int nrec, int r, int j0, const float *__restrict__ D,
+                                               const float *__restrict__ Z, double *__restrict__ P) {
+    const int s = blockIdx.y, seg = blockIdx.z;
+    const int i = (int)blockIdx.x * 64 + (int)threadIdx.x;
     if (i >= nrec) return;
+    const int len = (nt + kRfSeg - 1) / kRfSeg, t0 = seg * len, t1 = min(nt, t0 + len);
     const float *Ds = D + (int64_t)s * nt * nrec + i;
     const float *Zs = Z + (int64_t)s * nt * r + j0;
     double acc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0.0;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = t0; t < t1; ++t) {
         const double d = (double)Ds[(int64_t)t * nrec];
         const float *zr = Zs + (int64_t)t * r;
 #pragma unroll
         for (int c = 0; c < RC; ++c) acc[c] = fma(d, (double)zr[c], acc[c]);
     }
-    double *w = W + ((int64_t)s * nrec + i) * r + j0;
+    double *pp = P + (((int64_t)s * kRfSeg + seg) * nrec + i) * RC;
 #pragma unroll
-    for (int c = 0; c < RC; ++c) w[c] = acc[c];
+    for (int c = 0; c < RC; ++c) pp[c] = acc[c];
+}
+
+// W[s][i][j0 + c] = sum_seg P[s][seg][i][c], segments in order.
+template <int RC>
+__global__ __launch_bounds__(256) void k_rf_dtz_sum(int S, int nrec, int r, int j0, const double *__restrict__ P,
+                                                    double *__restrict__ W) {
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (int64_t)S * nrec) return;
+    const int s = (int)(idx / nrec), i = (int)(idx - (int64_t)s * nrec);
+#pragma unroll
+    for (int c = 0; c < RC; ++c) {
+        double acc = 0.0;
+        for (int seg = 0; seg < kRfSeg; ++seg) acc += P[(((int64_t)s * kRfSeg + seg) * nrec + i) * RC + c];
+        W[((int64_t)s * nrec + i) * r + j0 + c] = acc;
+    }
 }
 
 // Y[s][t][j0 + c] = sum_i D[s][t][i] W[s][i][j0 + c]: one wave per time
@@ -1492,97 +1514,138 @@ __global__ __launch_bounds__(256) void k_rf_dw(int nt, int nrec, int r, int j0, 
     }
 }
 
-// Householder QR of one shot's Y (nt x r, row-major) and the explicit
-// orthonormal factor, both in place (the unblocked LAPACK algorithms: the
-// reflector of column j is I - tau v v^T with v_j = 1, stored below the
-// diagonal; Q = H_0 ... H_{r-1} [I_r; 0] is then accumulated backwards).
-// Block = 1024 threads: 64 columns x 16 row groups for the column dot
-// products, summed over the row groups in a fixed order.  Q is written as
-// float [nt][r].
-__global__ __launch_bounds__(1024) void k_rf_qr(int nt, int r, double *__restrict__ Y, float *__restrict__ Q) {
-    const int s = blockIdx.x;
-    double *A = Y + (int64_t)s * nt * r;
-    const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-    __shared__ double red[1024];
-    __shared__ double tau[64];
-    __shared__ double wv[64];
-    __shared__ double scale;
+// ---------------------------------------------------------------------------
+// Tall-skinny QR of each shot's Y (nt x r, row-major), in FP64 with the
+// unblocked Householder algorithms (the reflector of column j is
+// I - tau v v^T with v_j = 1, stored below the diagonal):
+//   1. the rows are cut into P panels of at least r rows, each factored by
+//      its own block: Y_p = Q_p R_p;
+//   2. the stacked R_p (P r x r) are factored by one block per shot, and the
+//      explicit factor Q2 is formed in place (accumulated backwards);
+//   3. each panel's rows of Q are Q_p Q2_p = H_0 ... H_{r-1} [Q2_p; 0], the
+//      panel's reflectors applied backwards to its block of Q2.
+// Q = diag(Q_p) Q2 is orthonormal and spans Y's columns.  A block is 1024
+// threads: 64 columns x 16 row groups, fixed-order sums.
+// ---------------------------------------------------------------------------
+struct RfShared {
+    double red[1024];
+    double tau[64];
+    double wv[64];
+    double scale;
+};
 
-    auto block_sum = [&](double v) {   // fixed-order tree over the 1024 threads
-        red[tid] = v;
+__device__ double rf_block_sum(RfShared &sh, double v) {   // fixed-order tree over the block
+    const int tid = threadIdx.x;
+    sh.red[tid] = v;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+        if (tid < st) sh.red[tid] += sh.red[tid + st];
         __syncthreads();
-        for (int st = 512; st > 0; st >>= 1) {
-            if (tid < st) red[tid] += red[tid + st];
-            __syncthreads();
-        }
-        const double out = red[0];
-        __syncthreads();
-        return out;
-    };
-    // w_k = sum_{t >= j} v_t A[t][k] for k in (kmin, r), v_j = 1, v_t = A[t][j] below
-    auto column_dots = [&](int j, int kmin) {
-        double part = 0.0;
-        if (tx > kmin && tx < r)
-            for (int t = j + 1 + ty; t < nt; t += 16) part = fma(A[(int64_t)t * r + j], A[(int64_t)t * r + tx], part);
-        red[ty * 64 + tx] = part;
-        __syncthreads();
-        if (ty == 0 && tx > kmin && tx < r) {
-            double w = A[(int64_t)j * r + tx];
-            for (int g = 0; g < 16; ++g) w += red[g * 64 + tx];
-            wv[tx] = w;
-        }
-        __syncthreads();
-    };
-    // A[t][k] -= tau v_t w_k for t >= j, k in (kmin, r): thread (tx, ty) owns
-    // column tx and every 16th row (column j, read here, is not written)
-    auto apply = [&](int j, int kmin, double tj) {
-        if (tx > kmin && tx < r) {
-            const double wk = wv[tx];
-            for (int t = j + ty; t < nt; t += 16) {
-                const double vt = t == j ? 1.0 : A[(int64_t)t * r + j];
-                A[(int64_t)t * r + tx] -= tj * vt * wk;
-            }
-        }
-        __syncthreads();
-    };
+    }
+    const double out = sh.red[0];
+    __syncthreads();
+    return out;
+}
 
+// wv[k] = X[j][k] + sum_{t > j} V[t][j] X[t][k] for k in (kmin, r): v^T X with v_j = 1
+__device__ void rf_dots(RfShared &sh, const double *V, const double *X, int nrows, int r, int j, int kmin) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    double part = 0.0;
+    if (tx > kmin && tx < r)
+        for (int t = j + 1 + ty; t < nrows; t += 16) part = fma(V[(int64_t)t * r + j], X[(int64_t)t * r + tx], part);
+    sh.red[ty * 64 + tx] = part;
+    __syncthreads();
+    if (ty == 0 && tx > kmin && tx < r) {
+        double w = X[(int64_t)j * r + tx];
+        for (int g = 0; g < 16; ++g) w += sh.red[g * 64 + tx];
+        sh.wv[tx] = w;
+    }
+    __syncthreads();
+}
+
+// X[t][k] -= tau v_t wv[k] for t >= j, k in (kmin, r); column j of V is not written
+__device__ void rf_update(RfShared &sh, const double *V, double *X, int nrows, int r, int j, int kmin, double tj) {
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    if (tx > kmin && tx < r) {
+        const double wk = sh.wv[tx];
+        for (int t = j + ty; t < nrows; t += 16) {
+            const double vt = t == j ? 1.0 : V[(int64_t)t * r + j];
+            X[(int64_t)t * r + tx] -= tj * vt * wk;
+        }
+    }
+    __syncthreads();
+}
+
+// In-place Householder factorisation of A (nrows x r, nrows >= r); sh.tau holds the coefficients.
+__device__ void rf_householder(RfShared &sh, double *A, int nrows, int r) {
+    const int tid = threadIdx.x;
     for (int j = 0; j < r; ++j) {
         double part = 0.0;
-        for (int t = j + 1 + tid; t < nt; t += 1024) {
+        for (int t = j + 1 + tid; t < nrows; t += 1024) {
             const double x = A[(int64_t)t * r + j];
             part = fma(x, x, part);
         }
-        const double sigma = block_sum(part);
+        const double sigma = rf_block_sum(sh, part);
         if (tid == 0) {
             const double alpha = A[(int64_t)j * r + j];
             if (sigma == 0.0) {          // already upper triangular here: H_j = I
-                tau[j] = 0.0;
-                scale = 0.0;
+                sh.tau[j] = 0.0;
+                sh.scale = 0.0;
             } else {
                 const double norm = sqrt(fma(alpha, alpha, sigma));
                 const double beta = alpha >= 0.0 ? -norm : norm;
-                tau[j] = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
+                sh.tau[j] = (beta - alpha) / beta;
+                sh.scale = 1.0 / (alpha - beta);
                 A[(int64_t)j * r + j] = beta;
             }
         }
         __syncthreads();
-        const double tj = tau[j];
+        const double tj = sh.tau[j];
         if (tj != 0.0) {
-            for (int t = j + 1 + tid; t < nt; t += 1024) A[(int64_t)t * r + j] *= scale;
+            for (int t = j + 1 + tid; t < nrows; t += 1024) A[(int64_t)t * r + j] *= sh.scale;
             __syncthreads();
-            column_dots(j, j);
-            apply(j, j, tj);
+            rf_dots(sh, A, A, nrows, r, j, j);
+            rf_update(sh, A, A, nrows, r, j, j, tj);
         }
     }
-    // explicit Q, accumulated from the last reflector to the first
+}
+
+__device__ __forceinline__ void rf_panel_rows(int nt, int P, int p, int *row0, int *rows) {
+    const int m = nt / P;
+    *row0 = p * m;
+    *rows = p < P - 1 ? m : nt - (P - 1) * m;
+}
+
+__global__ __launch_bounds__(1024) void k_rf_panel_qr(int nt, int r, int P, double *__restrict__ Y,
+                                                      double *__restrict__ taus, double *__restrict__ Rs) {
+    __shared__ RfShared sh;
+    const int s = blockIdx.y, p = blockIdx.x, tid = threadIdx.x;
+    int row0, rows;
+    rf_panel_rows(nt, P, p, &row0, &rows);
+    double *A = Y + ((int64_t)s * nt + row0) * r;
+    rf_householder(sh, A, rows, r);
+    if (tid < r) taus[((int64_t)s * P + p) * r + tid] = sh.tau[tid];
+    double *Rp = Rs + ((int64_t)s * P + p) * r * r;
+    for (int idx = tid; idx < r * r; idx += 1024) {
+        const int i = idx / r, k = idx - i * r;
+        Rp[idx] = k >= i ? A[(int64_t)i * r + k] : 0.0;
+    }
+}
+
+// the stacked R factors of one shot -> Q2 in place (explicit, accumulated backwards)
+__global__ __launch_bounds__(1024) void k_rf_stack_qr(int r, int P, double *__restrict__ Rs) {
+    __shared__ RfShared sh;
+    const int s = blockIdx.x, tid = threadIdx.x;
+    const int nrows = P * r;
+    double *A = Rs + (int64_t)s * nrows * r;
+    rf_householder(sh, A, nrows, r);
     for (int j = r - 1; j >= 0; --j) {
-        const double tj = tau[j];
+        const double tj = sh.tau[j];
         if (j < r - 1 && tj != 0.0) {
-            column_dots(j, j);
-            apply(j, j, tj);
+            rf_dots(sh, A, A, nrows, r, j, j);
+            rf_update(sh, A, A, nrows, r, j, j, tj);
         }
-        for (int t = tid; t < nt; t += 1024) {
+        for (int t = tid; t < nrows; t += 1024) {
             double *a = &A[(int64_t)t * r + j];
             if (t < j) *a = 0.0;
             else if (t == j) *a = 1.0 - tj;
@@ -1590,19 +1653,67 @@ __global__ __launch_bounds__(1024) void k_rf_qr(int nt, int r, double *__restric
         }
         __syncthreads();
     }
-    float *Qs = Q + (int64_t)s * nt * r;
-    for (int64_t idx = tid; idx < (int64_t)nt * r; idx += 1024) Qs[idx] = (float)A[idx];
+}
+
+// rows of panel p of Q = H_0 ... H_{r-1} [Q2_p; 0], written as float
+__global__ __launch_bounds__(1024) void k_rf_panel_q(int nt, int r, int P, const double *__restrict__ Y,
+                                                     const double *__restrict__ taus, const double *__restrict__ Rs,
+                                                     double *__restrict__ B, float *__restrict__ Q) {
+    __shared__ RfShared sh;
+    const int s = blockIdx.y, p = blockIdx.x, tid = threadIdx.x;
+    int row0, rows;
+    rf_panel_rows(nt, P, p, &row0, &rows);
+    const double *V = Y + ((int64_t)s * nt + row0) * r;
+    double *X = B + ((int64_t)s * nt + row0) * r;
+    const double *Q2p = Rs + ((int64_t)s * P + p) * r * r;   // rows p r .. p r + r - 1 of Q2
+    for (int idx = tid; idx < rows * r; idx += 1024) X[idx] = idx < r * r ? Q2p[idx] : 0.0;
+    if (tid < r) sh.tau[tid] = taus[((int64_t)s * P + p) * r + tid];
+    __syncthreads();
+    for (int j = r - 1; j >= 0; --j) {
+        const double tj = sh.tau[j];
+        if (tj != 0.0) {
+            rf_dots(sh, V, X, rows, r, j, -1);
+            rf_update(sh, V, X, rows, r, j, -1, tj);
+        }
+    }
+    float *Qp = Q + ((int64_t)s * nt + row0) * r;
+    for (int idx = tid; idx < rows * r; idx += 1024) Qp[idx] = (float)X[idx];
+}
+
+// Panels per shot: about sqrt(nt / r) (balancing the panel and the stack
+// heights), at most 16, each panel at least r rows.
+int rf_panels(int nt, int r) {
+    int P = (int)std::lround(std::sqrt((double)nt / (double)r));
+    if (P > 16) P = 16;
+    while (P > 1 && nt / P < r) --P;
+    return P < 1 ? 1 : P;
+}
+
+size_t rf_scratch_doubles(int S, int nt, int nrec, int r) {
+    const int P = rf_panels(nt, r);
+    return (size_t)S * kRfSeg * nrec * 16      // segment partials of D^T Z
+           + (size_t)S * P * r                 // panel reflector coefficients
+           + (size_t)S * P * r * r             // stacked R factors, then Q2
+           + (size_t)S * nt * r;               // rows of Q in FP64
 }
 
 hipError_t launch_range_finder(int S, int nt, int nrec, int r, const float *d_obs, float *Z, double *W, double *Y,
-                               hipStream_t stream) {
+                               double *X, hipStream_t stream) {
     if (S < 1 || r < 1 || r > 64 || nrec < 1 || nt < r) return hipErrorInvalidValue;
-    const dim3 g1((unsigned)((nrec + 255) / 256), (unsigned)S), g2((unsigned)((nt + 3) / 4), (unsigned)S);
+    const int P = rf_panels(nt, r);
+    double *part = X;
+    double *taus = part + (size_t)S * kRfSeg * nrec * 16;
+    double *Rs = taus + (size_t)S * P * r;
+    double *Bq = Rs + (size_t)S * P * r * r;
+    const dim3 g1((unsigned)((nrec + 63) / 64), (unsigned)S, (unsigned)kRfSeg);
+    const dim3 g1s((unsigned)(((int64_t)S * nrec + 255) / 256));
+    const dim3 g2((unsigned)((nt + 3) / 4), (unsigned)S);
     for (int j0 = 0; j0 < r;) {
         int q = 16;
         while (q > r - j0) q >>= 1;   // power-of-two chunks of the probe columns
-#define TPX_RF(RC)                                                                                           \
-    hipLaunchKernelGGL(k_rf_dtz<RC>, g1, dim3(256), 0, stream, nt, nrec, r, j0, d_obs, (const float *)Z, W); \
+#define TPX_RF(RC)                                                                                                \
+    hipLaunchKernelGGL(k_rf_dtz<RC>, g1, dim3(64), 0, stream, nt, nrec, r, j0, d_obs, (const float *)Z, part);    \
+    hipLaunchKernelGGL(k_rf_dtz_sum<RC>, g1s, dim3(256), 0, stream, S, nrec, r, j0, (const double *)part, W);     \
     hipLaunchKernelGGL(k_rf_dw<RC>, g2, dim3(256), 0, stream, nt, nrec, r, j0, d_obs, (const double *)W, Y)
         switch (q) {
         case 16: TPX_RF(16); break;
@@ -1614,8 +1725,11 @@ hipError_t launch_range_finder(int S, int nt, int nrec, int r, const float *d_ob
 #undef TPX_RF
         j0 += q;
     }
-    // Z is read by the products above before the factorisation overwrites it with Q
-    hipLaunchKernelGGL(k_rf_qr, dim3((unsigned)S), dim3(1024), 0, stream, nt, r, Y, Z);
+    // Z is read by the products above before Q overwrites it
+    hipLaunchKernelGGL(k_rf_panel_qr, dim3((unsigned)P, (unsigned)S), dim3(1024), 0, stream, nt, r, P, Y, taus, Rs);
+    hipLaunchKernelGGL(k_rf_stack_qr, dim3((unsigned)S), dim3(1024), 0, stream, r, P, Rs);
+    hipLaunchKernelGGL(k_rf_panel_q, dim3((unsigned)P, (unsigned)S), dim3(1024), 0, stream, nt, r, P,
+                       (const double *)Y, (const double *)taus, (const double *)Rs, Bq, Z);
     return hipGetLastError();
 }
 

@@ -451,7 +451,7 @@ int default_block(const Layout &L, int nt, bool overlap, int r) {
 }
 
 struct Plan {
-    size_t flags, parts, J, beta, ring, hist, Z, zpk, rfW, rfY, ubar, vbar, gpart, res, d, tables, total;
+    size_t flags, parts, J, beta, ring, hist, Z, zpk, rfW, rfY, rfX, ubar, vbar, gpart, res, d, tables, total;
     int nslots, block;
     bool overlap;
 };
@@ -495,7 +495,8 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     if (mode == M_RANGE_FINDER) {   // FP64 scratch of the range finder only
         p.rfW = 0;
         p.rfY = align_up((size_t)L.S * P.nrec * pr->r * 8);
-        p.total = p.rfY + align_up((size_t)L.S * P.nt * pr->r * 8);
+        p.rfX = p.rfY + align_up((size_t)L.S * P.nt * pr->r * 8);
+        p.total = p.rfX + align_up(rf_scratch_doubles(L.S, P.nt, P.nrec, pr->r) * 8);
         return p;
     }
     const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
@@ -528,6 +529,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     if (probed && pr->kind == TPX_PROBE_RANGE_FINDER) {
         p.rfW = take((size_t)L.S * P.nrec * pr->r * 8);
         p.rfY = take((size_t)L.S * P.nt * pr->r * 8);
+        p.rfX = take(rf_scratch_doubles(L.S, P.nt, P.nrec, pr->r) * 8);
     }
     if (mode == M_GRAD_PROBED) p.ubar = take((size_t)L.S * r * L.nphys * 4);
     const bool keep_v = probed && pr->keep_vbar;
@@ -1026,7 +1028,7 @@ const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, const float *d_obs, t
     if (e == hipSuccess && rf)
         e = prof(KIND_OTHER, C.stream, [&] {
             return launch_range_finder(C.P.L.S, C.P.nt, C.P.nrec, pr->r, d_obs, Z, (double *)(C.ws + C.plan.rfW),
-                                       (double *)(C.ws + C.plan.rfY), C.stream);
+                                       (double *)(C.ws + C.plan.rfY), (double *)(C.ws + C.plan.rfX), C.stream);
         });
     const int mm = mfma_selected(pr);
     if (e == hipSuccess && (mm & MFMA_ACCUM)) {
@@ -1458,7 +1460,7 @@ tpx_status tpx_range_finder_probes(const tpx_grid *grid, const tpx_geom *geom, c
         const hipStream_t s = (hipStream_t)stream;
         TPX_HIP(launch_probe_gen(TPX_PROBE_RADEMACHER, probe->r, probe->seed, P.nt, 0, P.L.S, Q, s));
         TPX_HIP(launch_range_finder(P.L.S, P.nt, P.nrec, probe->r, d_obs, Q, (double *)(w + plan.rfW),
-                                    (double *)(w + plan.rfY), s));
+                                    (double *)(w + plan.rfY), (double *)(w + plan.rfX), s));
         return TPX_OK;
     });
 }

@@ -169,10 +169,11 @@ hipError_t launch_image_probed(const Layout &L, int r, float c, const float *uba
 hipError_t launch_image_graddot(const Layout &L, double h, int r, float c, const float *ubar, const float *vbar,
                                 float *g, hipStream_t stream);
 // Probes from the range of the data covariance: Z[S][nt][r] holds the shots'
-// Rademacher probes on entry and Q = qr(D D^T Z) on exit.  W (S*nrec*r) and Y
-// (S*nt*r) are FP64 scratch.  r <= 64, nt >= r.
+// Rademacher probes on entry and Q = qr(D D^T Z) on exit.  W (S*nrec*r), Y
+// (S*nt*r) and X (rf_scratch_doubles) are FP64 scratch.  r <= 64, nt >= r.
+size_t rf_scratch_doubles(int S, int nt, int nrec, int r);   // X below, in doubles
 hipError_t launch_range_finder(int S, int nt, int nrec, int r, const float *d_obs, float *Z, double *W, double *Y,
-                               hipStream_t stream);
+                               double *X, hipStream_t stream);
 // res = d - d_obs; J = 1/2 sum res^2 (deterministic two-pass FP64 reduction)
 hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_t n, double *partials,
                            int nparts, double *J, hipStream_t stream);
