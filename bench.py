@@ -317,7 +317,7 @@ def matrix_core_use(kind: str, r: int, keep_vbar: bool) -> str:
     """Which contractions run on the matrix cores under the library option."""
     from paper_2104_00794_amd import tpx
     opt = tpx.get_option(tpx.OPT_MATRIX_CORES)
-    if kind not in ("rademacher", "gauss_b64") or r % 16 != 0 or opt == 0:
+    if r % 16 != 0 or opt == 0:
         return "none"
     accum = opt == 2 or r >= 64
     fold = not keep_vbar and (opt == 2 or r >= 32)

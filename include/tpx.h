@@ -225,14 +225,16 @@ void tpx_job_destroy(tpx_job *job);
 enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2 };
 /* TPX_OPT_MATRIX_CORES (default 1): the probe contractions of the time
  * blocks are dense products (r x b by b x points) and can run on the matrix
- * cores (bfloat16 MFMA with each FP32 field value split exactly into three
- * bfloat16 parts, FP32 accumulation) when the probes are Rademacher or
- * GAUSS_B64 (entries exact in bfloat16) and r is a multiple of 16.  Value 0:
- * never; 1: the folded adjoint contraction when r >= 32 and the ubar/vbar
- * accumulations when r >= 64 (where they measured faster than the vector
- * units); 2: every contraction.  Other probes always use the FP32 vector-unit
- * contractions.  Results agree with the FP32 path to rounding (not bitwise).
- * Workspace sizes do not depend on this option. */
+ * cores when r is a multiple of 16: bfloat16 MFMA with each FP32 field value
+ * split exactly into three bfloat16 parts and FP32 accumulation.  Probes exact
+ * in bfloat16 (Rademacher, GAUSS_B64, identity) take three products per tile;
+ * other probes (explicit, range finder) are split in three as well and take
+ * six, the dropped terms below 2^-21 of each product.  Value 0: never; 1: the
+ * folded adjoint contraction when r >= 32 and the ubar/vbar accumulations
+ * when r >= 64 (where they measured faster than the vector units); 2: every
+ * contraction.  Explicit probes must be 16-byte aligned to qualify.  Results
+ * agree with the FP32 path to rounding (not bitwise).  Workspace sizes do
+ * not depend on this option. */
 tpx_status tpx_set_option(int32_t option, int64_t value);
 int64_t tpx_get_option(int32_t option);
 

@@ -886,6 +886,28 @@ __device__ __forceinline__ floatx4 mfma_bf16x3(shortx4 a, shortx4 bh, shortx4 bm
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bh, d, 0, 0, 0);
 }
 
+// Both operands split in three (probes that are not exact in bfloat16): the
+// six products down to the order of 2^-14 relative, smallest first; the
+// three dropped terms are below 2^-21 of the product.
+__device__ __forceinline__ floatx4 mfma_bf16x6(shortx4 ah, shortx4 am, shortx4 al, shortx4 bh, shortx4 bm,
+                                               shortx4 bl, floatx4 d) {
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bm, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am, bh, d, 0, 0, 0);
+    d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bm, d, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, d, 0, 0, 0);
+}
+
+__device__ __forceinline__ shortx4 unpack_bf16x4(uint2 z) {
+    shortx4 a;
+    a[0] = (short)(z.x & 0xffffu);
+    a[1] = (short)(z.x >> 16);
+    a[2] = (short)(z.y & 0xffffu);
+    a[3] = (short)(z.y >> 16);
+    return a;
+}
+
 __device__ __forceinline__ int ring_slot(int s, int nslots) { return ((s % nslots) + nslots) % nslots; }
 
 // The buffered levels behind one 16-level group at this lane's four points:
@@ -939,9 +961,10 @@ __device__ __forceinline__ void group_values(const GroupLoads<SD> &G, int s_lo, 
     }
 }
 
-// Probe rows in the A-operand order: zpk[shot][kg][mt][lane] holds
-// Z[16 kg + 4 g + q][16 mt + n], q = 0..3, as four bfloat16 (zero past nt).
-__global__ __launch_bounds__(256) void k_pack_probes(int S, int nt, int r, const float *__restrict__ Z,
+// Probe rows in the A-operand order: zpk[part][shot][kg][mt][lane] holds
+// Z[16 kg + 4 g + q][16 mt + n], q = 0..3, as four bfloat16 (zero past nt);
+// with three parts, the exact three-way split of each value.
+__global__ __launch_bounds__(256) void k_pack_probes(int S, int nt, int r, int parts, const float *__restrict__ Z,
                                                      uint2 *__restrict__ zpk) {
     const int nkg = (nt + 15) / 16, nm = r / 16;
     const int64_t total = (int64_t)S * nkg * nm * 64;
@@ -954,19 +977,25 @@ __global__ __launch_bounds__(256) void k_pack_probes(int S, int nt, int r, const
     const int kg = (int)(rest % nkg);
     const int shot = (int)(rest / nkg);
     const int g = lane >> 4, n = lane & 15;
-    unsigned v[4];
+    float z[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int s = 16 * kg + 4 * g + q;
-        const float z = s < nt ? Z[((int64_t)shot * nt + s) * r + 16 * mt + n] : 0.0f;
-        v[q] = __float_as_uint(z) >> 16;
+        z[q] = s < nt ? Z[((int64_t)shot * nt + s) * r + 16 * mt + n] : 0.0f;
     }
-    zpk[idx] = make_uint2(v[0] | (v[1] << 16), v[2] | (v[3] << 16));
+    shortx4 h, m, l;
+    split_bf16x3(z, h, m, l);
+    const shortx4 pv[3] = {h, m, l};
+    for (int part = 0; part < parts; ++part) {
+        const shortx4 v = pv[part];
+        zpk[part * total + idx] = make_uint2((unsigned)(unsigned short)v[0] | ((unsigned)(unsigned short)v[1] << 16),
+                                             (unsigned)(unsigned short)v[2] | ((unsigned)(unsigned short)v[3] << 16));
+    }
 }
 
 // acc_j += sum_s Z[s, j] x^s for the RM x 16 probes j0 ..: ubar (forward) or
 // vbar (adjoint), x^s as in block_values.
-template <int RM, int SD>
+template <int RM, int SD, int ZS>
 __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float *__restrict__ ring, int nslots,
                                                     int s_lo, int s_hi, const uint2 *__restrict__ zpk, int nkg,
                                                     int r, int j0, float *__restrict__ out) {
@@ -984,6 +1013,7 @@ __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float 
     }
     const float *base = ring + (int64_t)shot * L.shot_floats;
     const int nm = r / 16;
+    const int64_t part_stride = (int64_t)gridDim.y * nkg * nm * 64;   // gridDim.y = shots
     const uint2 *zs = zpk + (int64_t)shot * nkg * nm * 64 + (j0 / 16) * 64 + lane;
     floatx4 acc[RM][4];
 #pragma unroll
@@ -993,11 +1023,13 @@ __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float 
     const int kg_lo = s_lo >> 4, kg_hi = s_hi >> 4;
     const int step16 = 16 % nslots;
     int sl = ring_slot(16 * kg_lo + 4 * g - SD, nslots);
-    auto zload = [&](int kg, uint2 (&zz)[RM]) {
+    auto zload = [&](int kg, uint2 (&zz)[RM * ZS]) {
 #pragma unroll
-        for (int mt = 0; mt < RM; ++mt) zz[mt] = zs[((int64_t)kg * nm + mt) * 64];
+        for (int p = 0; p < ZS; ++p)
+#pragma unroll
+            for (int mt = 0; mt < RM; ++mt) zz[p * RM + mt] = zs[p * part_stride + ((int64_t)kg * nm + mt) * 64];
     };
-    auto contract = [&](const GroupLoads<SD> &G, const uint2 (&zz)[RM], int kg) {
+    auto contract = [&](const GroupLoads<SD> &G, const uint2 (&zz)[RM * ZS], int kg) {
         float x[4][4];
         group_values<SD>(G, s_lo, s_hi, 16 * kg + 4 * g, ok, x);
         shortx4 bh[4], bm[4], bl[4];
@@ -1005,13 +1037,15 @@ __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float 
         for (int t = 0; t < 4; ++t) split_bf16x3(x[t], bh[t], bm[t], bl[t]);
 #pragma unroll
         for (int mt = 0; mt < RM; ++mt) {
-            shortx4 a;
-            a[0] = (short)(zz[mt].x & 0xffffu);
-            a[1] = (short)(zz[mt].x >> 16);
-            a[2] = (short)(zz[mt].y & 0xffffu);
-            a[3] = (short)(zz[mt].y >> 16);
+            const shortx4 a = unpack_bf16x4(zz[mt]);
+            if (ZS == 1) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) acc[mt][t] = mfma_bf16x3(a, bh[t], bm[t], bl[t], acc[mt][t]);
+                for (int t = 0; t < 4; ++t) acc[mt][t] = mfma_bf16x3(a, bh[t], bm[t], bl[t], acc[mt][t]);
+            } else {
+                const shortx4 am = unpack_bf16x4(zz[RM + mt]), al = unpack_bf16x4(zz[2 * RM + mt]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[mt][t] = mfma_bf16x6(a, am, al, bh[t], bm[t], bl[t], acc[mt][t]);
+            }
         }
     };
     // Software pipeline over two register sets: the loads of group kg + 1 are
@@ -1019,8 +1053,8 @@ __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float 
     // there), so the wait for group kg leaves the next group's loads in
     // flight.  The loop is unrolled twice so no set is copied.
     GroupLoads<SD> ga, gb;
-    uint2 za[RM], zb[RM];
-    auto prefetch = [&](int kg, GroupLoads<SD> &G, uint2 (&zz)[RM]) {
+    uint2 za[RM * ZS], zb[RM * ZS];
+    auto prefetch = [&](int kg, GroupLoads<SD> &G, uint2 (&zz)[RM * ZS]) {
         sl += step16;
         if (sl >= nslots) sl -= nslots;
         group_load<SD>(base, (uint32_t)L.slot_floats, nslots, sl, off, G);
@@ -1060,7 +1094,7 @@ __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float 
 // per 16 levels, Y (16 levels x 16 points) = Z (levels x probes) . ubar
 // (probes x points) on the matrix cores, then the level sum against x^s in
 // FP32 and a fixed-order sum over the four lane groups.
-template <int RK, int SD>
+template <int RK, int SD, int ZS>
 __global__ __launch_bounds__(256) void k_fold_mfma(const Layout L, const float *__restrict__ ring, int nslots,
                                                    int s_lo, int s_hi, const float *__restrict__ Z, int nt, int r,
                                                    int j0, const float *__restrict__ ubar, float c,
@@ -1110,13 +1144,17 @@ __global__ __launch_bounds__(256) void k_fold_mfma(const Layout L, const float *
         for (int t = 0; t < 4; ++t) d[t] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int kt = 0; kt < RK; ++kt) {
-            shortx4 a;
-            a[0] = zin ? (short)(__float_as_uint(zv[kt].x) >> 16) : (short)0;
-            a[1] = zin ? (short)(__float_as_uint(zv[kt].y) >> 16) : (short)0;
-            a[2] = zin ? (short)(__float_as_uint(zv[kt].z) >> 16) : (short)0;
-            a[3] = zin ? (short)(__float_as_uint(zv[kt].w) >> 16) : (short)0;
+            const float zf[4] = {zin ? zv[kt].x : 0.0f, zin ? zv[kt].y : 0.0f, zin ? zv[kt].z : 0.0f,
+                                 zin ? zv[kt].w : 0.0f};
+            shortx4 ah, am, al;
+            split_bf16x3(zf, ah, am, al);
+            if (ZS == 1) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) d[t] = mfma_bf16x3(a, uh[kt][t], um[kt][t], ul[kt][t], d[t]);
+                for (int t = 0; t < 4; ++t) d[t] = mfma_bf16x3(ah, uh[kt][t], um[kt][t], ul[kt][t], d[t]);
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) d[t] = mfma_bf16x6(ah, am, al, uh[kt][t], um[kt][t], ul[kt][t], d[t]);
+            }
         }
         float x[4][4];
         group_values<SD>(G, s_lo, s_hi, 16 * kg + 4 * g, ok, x);
@@ -1226,22 +1264,25 @@ hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int 
     return hipGetLastError();
 }
 
-size_t pack_probes_bytes(int S, int nt, int r) { return (size_t)S * ((nt + 15) / 16) * (r / 16) * 64 * 8; }
+size_t pack_probes_bytes(int S, int nt, int r, int parts) {
+    return (size_t)parts * S * ((nt + 15) / 16) * (r / 16) * 64 * 8;
+}
 
-hipError_t launch_pack_probes(int S, int nt, int r, const float *Z, void *zpk, hipStream_t stream) {
+hipError_t launch_pack_probes(int S, int nt, int r, int parts, const float *Z, void *zpk, hipStream_t stream) {
     const int64_t total = (int64_t)S * ((nt + 15) / 16) * (r / 16) * 64;
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_probes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, S, nt, r, Z,
-                       (uint2 *)zpk);
+    if (parts != 1 && parts != 3) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_probes, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, S, nt, r, parts,
+                       Z, (uint2 *)zpk);
     return hipGetLastError();
 }
 
-template <int SD>
+template <int SD, int ZS>
 static void launch_accum_mfma_sd(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots,
                                  int s_lo, int s_hi, const uint2 *zpk, int nkg, int r, float *out) {
     for (int j0 = 0; j0 < r;) {
         const int rm = std::min(4, (r - j0) / 16);
-#define TPX_MF(RM) hipLaunchKernelGGL((k_accum_mfma<RM, SD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, zpk, nkg, r, j0, out)
+#define TPX_MF(RM) hipLaunchKernelGGL((k_accum_mfma<RM, SD, ZS>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, zpk, nkg, r, j0, out)
         switch (rm) {
         case 4: TPX_MF(4); break;
         case 3: TPX_MF(3); break;
@@ -1254,22 +1295,28 @@ static void launch_accum_mfma_sd(const Layout &L, dim3 g, hipStream_t stream, co
 }
 
 hipError_t launch_accum_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const void *zpk,
-                             int nt, int r, int sd, float *out, hipStream_t stream) {
+                             int parts, int nt, int r, int sd, float *out, hipStream_t stream) {
     if (s_hi < s_lo) return hipSuccess;
-    if (r % 16 != 0 || s_lo < 0) return hipErrorInvalidValue;
+    if (r % 16 != 0 || s_lo < 0 || (parts != 1 && parts != 3)) return hipErrorInvalidValue;
     const dim3 g = point_grid(L);
     const int nkg = (nt + 15) / 16;
-    if (sd) launch_accum_mfma_sd<1>(L, g, stream, ring, nslots, s_lo, s_hi, (const uint2 *)zpk, nkg, r, out);
-    else launch_accum_mfma_sd<0>(L, g, stream, ring, nslots, s_lo, s_hi, (const uint2 *)zpk, nkg, r, out);
+    const uint2 *zp = (const uint2 *)zpk;
+    if (parts == 1) {
+        if (sd) launch_accum_mfma_sd<1, 1>(L, g, stream, ring, nslots, s_lo, s_hi, zp, nkg, r, out);
+        else launch_accum_mfma_sd<0, 1>(L, g, stream, ring, nslots, s_lo, s_hi, zp, nkg, r, out);
+    } else {
+        if (sd) launch_accum_mfma_sd<1, 3>(L, g, stream, ring, nslots, s_lo, s_hi, zp, nkg, r, out);
+        else launch_accum_mfma_sd<0, 3>(L, g, stream, ring, nslots, s_lo, s_hi, zp, nkg, r, out);
+    }
     return hipGetLastError();
 }
 
-template <int SD>
+template <int SD, int ZS>
 static void launch_fold_mfma_sd(const Layout &L, dim3 g, hipStream_t stream, const float *ring, int nslots, int s_lo,
                                 int s_hi, const float *Z, int nt, int r, const float *ubar, float c, float *gpart) {
     for (int j0 = 0; j0 < r;) {
         const int rk = std::min(4, (r - j0) / 16);
-#define TPX_FM(RK) hipLaunchKernelGGL((k_fold_mfma<RK, SD>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar, c, gpart)
+#define TPX_FM(RK) hipLaunchKernelGGL((k_fold_mfma<RK, SD, ZS>), g, dim3(256), 0, stream, L, ring, nslots, s_lo, s_hi, Z, nt, r, j0, ubar, c, gpart)
         switch (rk) {
         case 4: TPX_FM(4); break;
         case 3: TPX_FM(3); break;
@@ -1281,13 +1328,20 @@ static void launch_fold_mfma_sd(const Layout &L, dim3 g, hipStream_t stream, con
     }
 }
 
-hipError_t launch_fold_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z, int nt,
-                            int r, int sd, const float *ubar, float c, float *gpart, hipStream_t stream) {
+hipError_t launch_fold_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,
+                            int parts, int nt, int r, int sd, const float *ubar, float c, float *gpart,
+                            hipStream_t stream) {
     if (s_hi < s_lo) return hipSuccess;
-    if (r % 16 != 0 || s_lo < 0) return hipErrorInvalidValue;
+    if (r % 16 != 0 || s_lo < 0 || (parts != 1 && parts != 3) || ((uintptr_t)Z & 15) != 0)
+        return hipErrorInvalidValue;
     const dim3 g = point_grid(L);
-    if (sd) launch_fold_mfma_sd<1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
-    else launch_fold_mfma_sd<0>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
+    if (parts == 1) {
+        if (sd) launch_fold_mfma_sd<1, 1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
+        else launch_fold_mfma_sd<0, 1>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
+    } else {
+        if (sd) launch_fold_mfma_sd<1, 3>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
+        else launch_fold_mfma_sd<0, 3>(L, g, stream, ring, nslots, s_lo, s_hi, Z, nt, r, ubar, c, gpart);
+    }
     return hipGetLastError();
 }
 

@@ -458,10 +458,15 @@ struct Plan {
 
 enum Mode { M_FORWARD, M_ADJOINT, M_GRAD_PROBED, M_GRAD_FULL, M_FWD_PROBED, M_BWD_PROBED, M_RANGE_FINDER, M_OBJECTIVE };
 
-// Probes whose entries are exact in bfloat16 (counter-hash kinds) and whose
-// count is a multiple of 16 can be contracted on the matrix cores.
-bool mfma_eligible(const tpx_probe *pr) {
-    return pr && (pr->kind == TPX_PROBE_RADEMACHER || pr->kind == TPX_PROBE_GAUSS_B64) && pr->r % 16 == 0;
+// Probes whose count is a multiple of 16 can be contracted on the matrix
+// cores: in one bfloat16 part when their entries are exact in bfloat16 (the
+// counter-hash kinds and the identity), split in three parts otherwise.
+bool mfma_eligible(const tpx_probe *pr) { return pr && pr->r % 16 == 0; }
+
+int probe_parts(const tpx_probe *pr) {
+    const bool exact = pr->kind == TPX_PROBE_RADEMACHER || pr->kind == TPX_PROBE_GAUSS_B64 ||
+                       pr->kind == TPX_PROBE_IDENTITY;
+    return exact ? 1 : 3;
 }
 
 enum { MFMA_ACCUM = 1, MFMA_FOLD = 2 };
@@ -469,6 +474,8 @@ enum { MFMA_ACCUM = 1, MFMA_FOLD = 2 };
 int mfma_selected(const tpx_probe *pr) {
     const int opt = g_mfma.load();
     if (!mfma_eligible(pr) || opt == 0) return 0;
+    // the fold reads the caller's explicit probes as 16-byte vectors
+    if (pr->kind == TPX_PROBE_EXPLICIT && ((uintptr_t)pr->Z & 15) != 0) return 0;
     if (opt == 2) return MFMA_ACCUM | MFMA_FOLD;
     return (pr->r >= 64 ? MFMA_ACCUM : 0) | (pr->r >= 32 ? MFMA_FOLD : 0);
 }
@@ -525,7 +532,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     p.ring = take(slot * p.nslots);
     if (mode == M_GRAD_FULL) p.hist = take(slot * (size_t)P.nt);
     if (probed && pr->kind != TPX_PROBE_EXPLICIT) p.Z = take((size_t)L.S * P.nt * r * 4);
-    if (probed && mfma_eligible(pr)) p.zpk = take(pack_probes_bytes(L.S, P.nt, r));
+    if (probed && mfma_eligible(pr)) p.zpk = take(pack_probes_bytes(L.S, P.nt, r, probe_parts(pr)));
     if (probed && pr->kind == TPX_PROBE_RANGE_FINDER) {
         p.rfW = take((size_t)L.S * P.nrec * pr->r * 8);
         p.rfY = take((size_t)L.S * P.nt * pr->r * 8);
@@ -560,6 +567,7 @@ struct Ctx {
     float *ring = nullptr;
     const void *zpk = nullptr;   // packed probes when the accumulations run on the matrix cores
     bool fold_mfma = false;      // the folded adjoint contraction runs on the matrix cores
+    int zparts = 1;              // bfloat16 parts per probe value on the matrix cores
     // overlap of the contractions: auxiliary stream and per-block events
     // (block i uses slot i & 1; the main stream waits for block i's
     // contraction before block i + 2 starts overwriting its ring slots)
@@ -829,8 +837,9 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
             // differences centred at k = s_lo-1..s_hi-1, which they complete (dtt 1)
             auto contract = [&](hipStream_t cs) {
                 if (C.zpk)
-                    return f.dtt ? launch_accum_mfma(L, f.buf, f.ns, s_lo - 1, s_hi - 1, C.zpk, nt, f.r, 1, f.ubar, cs)
-                                 : launch_accum_mfma(L, f.buf, f.ns, s_lo, s_hi, C.zpk, nt, f.r, 0, f.ubar, cs);
+                    return f.dtt ? launch_accum_mfma(L, f.buf, f.ns, s_lo - 1, s_hi - 1, C.zpk, C.zparts, nt, f.r, 1,
+                                                     f.ubar, cs)
+                                 : launch_accum_mfma(L, f.buf, f.ns, s_lo, s_hi, C.zpk, C.zparts, nt, f.r, 0, f.ubar, cs);
                 return f.dtt ? launch_accum_adj(L, f.buf, f.ns, s_lo - 1, s_hi - 1, f.Z, nt, f.r, 0, 1, nullptr, 1.0f,
                                                 f.ubar, nullptr, cs)
                              : launch_accum_fwd(L, f.buf, f.ns, s_lo, s_hi, f.Z, nt, f.r, f.ubar, cs);
@@ -974,8 +983,10 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
                 if (o.hist) return launch_accum_full(L, o.hist, C.ring, ns, k_last, s_hi, o.gpart, cs);
                 const int sd = o.dtt ? 0 : 1;
                 if (o.fold && C.fold_mfma)
-                    return launch_fold_mfma(L, C.ring, ns, lo, hi, o.Z, nt, o.r, sd, o.ubar, o.c, o.gpart, cs);
-                if (!o.fold && C.zpk) return launch_accum_mfma(L, C.ring, ns, lo, hi, C.zpk, nt, o.r, sd, o.vbar, cs);
+                    return launch_fold_mfma(L, C.ring, ns, lo, hi, o.Z, C.zparts, nt, o.r, sd, o.ubar, o.c, o.gpart,
+                                            cs);
+                if (!o.fold && C.zpk)
+                    return launch_accum_mfma(L, C.ring, ns, lo, hi, C.zpk, C.zparts, nt, o.r, sd, o.vbar, cs);
                 return launch_accum_adj(L, C.ring, ns, lo, hi, o.Z, nt, o.r, o.fold, sd, o.ubar, o.c, o.vbar,
                                         o.gpart, cs);
             };
@@ -1016,29 +1027,34 @@ tpx_status run_adjoint(Ctx &C, const float *amp, const AdjOut &o) {
 // the counter hash, or (RANGE_FINDER) the QR factor of D_obs D_obs^T Z.
 const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, const float *d_obs, tpx_status *st) {
     *st = TPX_OK;
-    if (pr->kind == TPX_PROBE_EXPLICIT) return pr->Z;
-    float *Z = (float *)(C.ws + C.plan.Z);
-    const bool rf = pr->kind == TPX_PROBE_RANGE_FINDER;
-    if (rf && !d_obs) {
-        *st = fail(TPX_E_INVAL, "range-finder probes need the observed data");
-        return nullptr;
+    hipError_t e = hipSuccess;
+    const float *Zc = pr->Z;
+    if (pr->kind != TPX_PROBE_EXPLICIT) {
+        float *Z = (float *)(C.ws + C.plan.Z);
+        const bool rf = pr->kind == TPX_PROBE_RANGE_FINDER;
+        if (rf && !d_obs) {
+            *st = fail(TPX_E_INVAL, "range-finder probes need the observed data");
+            return nullptr;
+        }
+        const int kind = rf ? TPX_PROBE_RADEMACHER : pr->kind;
+        e = prof(KIND_OTHER, C.stream, [&] { return launch_probe_gen(kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream); });
+        if (e == hipSuccess && rf)
+            e = prof(KIND_OTHER, C.stream, [&] {
+                return launch_range_finder(C.P.L.S, C.P.nt, C.P.nrec, pr->r, d_obs, Z, (double *)(C.ws + C.plan.rfW),
+                                           (double *)(C.ws + C.plan.rfY), (double *)(C.ws + C.plan.rfX), C.stream);
+            });
+        Zc = Z;
     }
-    const int kind = rf ? TPX_PROBE_RADEMACHER : pr->kind;
-    hipError_t e = prof(KIND_OTHER, C.stream, [&] { return launch_probe_gen(kind, pr->r, pr->seed, C.P.nt, 0, C.P.L.S, Z, C.stream); });
-    if (e == hipSuccess && rf)
-        e = prof(KIND_OTHER, C.stream, [&] {
-            return launch_range_finder(C.P.L.S, C.P.nt, C.P.nrec, pr->r, d_obs, Z, (double *)(C.ws + C.plan.rfW),
-                                       (double *)(C.ws + C.plan.rfY), (double *)(C.ws + C.plan.rfX), C.stream);
-        });
     const int mm = mfma_selected(pr);
+    C.zparts = mfma_eligible(pr) ? probe_parts(pr) : 1;
     if (e == hipSuccess && (mm & MFMA_ACCUM)) {
         void *zpk = C.ws + C.plan.zpk;
-        e = prof(KIND_OTHER, C.stream, [&] { return launch_pack_probes(C.P.L.S, C.P.nt, pr->r, Z, zpk, C.stream); });
+        e = prof(KIND_OTHER, C.stream, [&] { return launch_pack_probes(C.P.L.S, C.P.nt, pr->r, C.zparts, Zc, zpk, C.stream); });
         C.zpk = zpk;
     }
     C.fold_mfma = (mm & MFMA_FOLD) != 0;
     if (e != hipSuccess) *st = fail(TPX_E_DEVICE, std::string("probe generation: ") + hipGetErrorString(e));
-    return Z;
+    return Zc;
 }
 
 // Imaging of the probed fields: pointwise (Eq. 4) or through the gradient (Eq. 5).

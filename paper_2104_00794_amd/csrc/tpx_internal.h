@@ -145,18 +145,21 @@ hipError_t launch_accum_fwd(const Layout &L, const float *ring, int nslots, int 
 hipError_t launch_accum_adj(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi,
                             const float *Z, int nt, int r, int fold, int sd, const float *ubar, float c,
                             float *vbar, float *gpart, hipStream_t stream);
-// The same contractions on the matrix cores, for probes exact in bfloat16
-// and r a multiple of 16.  zpk: the probes packed by launch_pack_probes
-// (S * ceil(nt/16) * r/16 * 64 entries of 8 bytes).
+// The same contractions on the matrix cores, r a multiple of 16.  parts = 1
+// for probes exact in bfloat16 (three bf16 products per tile), 3 for any
+// other probes (each value split in three; six products).  zpk: the probes
+// packed by launch_pack_probes (parts * S * ceil(nt/16) * r/16 * 64 entries of
+// 8 bytes).
 //   out[shot][j][p] += sum_s Z[shot][s][j] w^s[p]      (launch_accum_mfma)
-//   gpart[shot][p]  += -c sum_s w^s[p] sum_j Z[s][j] ubar_j[p]   (launch_fold_mfma, Z as floats)
+//   gpart[shot][p]  += -c sum_s w^s[p] sum_j Z[s][j] ubar_j[p]   (launch_fold_mfma, Z as floats, 16-byte aligned)
 // w^s as above (sd selects the second difference); s_lo >= 0.
-size_t pack_probes_bytes(int S, int nt, int r);
-hipError_t launch_pack_probes(int S, int nt, int r, const float *Z, void *zpk, hipStream_t stream);
+size_t pack_probes_bytes(int S, int nt, int r, int parts);
+hipError_t launch_pack_probes(int S, int nt, int r, int parts, const float *Z, void *zpk, hipStream_t stream);
 hipError_t launch_accum_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const void *zpk,
-                             int nt, int r, int sd, float *out, hipStream_t stream);
-hipError_t launch_fold_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z, int nt,
-                            int r, int sd, const float *ubar, float c, float *gpart, hipStream_t stream);
+                             int parts, int nt, int r, int sd, float *out, hipStream_t stream);
+hipError_t launch_fold_mfma(const Layout &L, const float *ring, int nslots, int s_lo, int s_hi, const float *Z,
+                            int parts, int nt, int r, int sd, const float *ubar, float c, float *gpart,
+                            hipStream_t stream);
 // gpart[shot][p] += - sum_s u^s[p] w^s[p], u^s from the full history (slot s)
 hipError_t launch_accum_full(const Layout &L, const float *hist, const float *ring, int nslots, int s_lo,
                              int s_hi, float *gpart, hipStream_t stream);

@@ -28,7 +28,7 @@ def test_matrix_core_record_follows_the_library_option():
         assert bench.matrix_core_use("rademacher", 32, False) == "fold"
         assert bench.matrix_core_use("rademacher", 64, False) == "ubar+fold"
         assert bench.matrix_core_use("gauss_b64", 64, True) == "ubar+vbar"
-        assert bench.matrix_core_use("range_finder", 64, False) == "none"
+        assert bench.matrix_core_use("range_finder", 64, False) == "ubar+fold"
         assert bench.matrix_core_use("rademacher", 40, False) == "none"
         tpx.set_option(tpx.OPT_MATRIX_CORES, 2)
         assert bench.matrix_core_use("rademacher", 16, True) == "ubar+vbar"

@@ -96,3 +96,22 @@ def test_matrix_core_split_and_job_paths_are_bitwise_equal():
     assert np.array_equal(to_np(g), to_np(g_job))
     # the split pair images the same residual (d - d_obs) with the same kernels
     assert np.array_equal(to_np(g_split), to_np(g))
+
+
+@pytest.mark.parametrize("r,keep_vbar,side", [(32, False, 0), (32, True, 1), (48, False, 1), (16, True, 0)])
+def test_split_probes_on_the_matrix_cores_match_oracle(r, keep_vbar, side):
+    # explicit probes with arbitrary FP32 entries: each probe value is split in
+    # three bfloat16 parts as well (six products per tile)
+    _print_case("mfma_split_probes", r=r, keep_vbar=keep_vbar, side=side)
+    c = Case(small_2d(nz=40, nx=150, nt=220, nshots=3, nrec=17))
+    dobs = c.dobs_oracle()
+    rng = np.random.default_rng(r + 7)
+    Z = rng.standard_normal((c.wl.nshots, c.wl.nt, r)).astype(np.float32).astype(np.float64)
+    g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, kind="explicit", r=r, Z=Z,
+                                    scale=1.0 / r, side=side)
+    probe = tpx.Probe(kind="explicit", r=r, Z=cuda(Z), scale=1.0 / r, block=37, keep_vbar=keep_vbar, dtt_side=side)
+    m, d = cuda(c.m0), cuda(dobs)
+    g_m, _ = _with_option(2, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d))
+    g_v, _ = _with_option(0, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d))
+    assert rel_l2(to_np(g_m), g_o) <= TOL
+    assert rel_l2(to_np(g_m), to_np(g_v)) <= 1e-5
