@@ -690,14 +690,9 @@ __device__ __forceinline__ PointIndex point_index(const Layout &L) {
 
 constexpr int kAccUnroll = 8;   // buffered steps whose loads are issued together
 
-// Buffered slots are read exactly once by a contraction.
-__device__ __forceinline__ float ring_load(const float *p) {
-#ifdef TPX_RING_NT
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
+// Buffered slots are read exactly once by a contraction (plain loads: a
+// nontemporal hint measured no faster).
+__device__ __forceinline__ float ring_load(const float *p) { return *p; }
 
 // Forward contraction of exactly RC probes j0..j0+RC-1 (no per-probe
 // predicates: the launcher splits r into power-of-two chunks).
@@ -994,7 +989,7 @@ __global__ __launch_bounds__(256) void k_pack_probes(int S, int nt, int r, int p
 }
 
 // acc_j += sum_s Z[s, j] x^s for the RM x 16 probes j0 ..: ubar (forward) or
-// vbar (adjoint), x^s as in block_values.
+// vbar (adjoint), x^s as in group_values.
 template <int RM, int SD, int ZS>
 __global__ __launch_bounds__(256) void k_accum_mfma(const Layout L, const float *__restrict__ ring, int nslots,
                                                     int s_lo, int s_hi, const uint2 *__restrict__ zpk, int nkg,
