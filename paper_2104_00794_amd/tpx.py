@@ -11,7 +11,7 @@ import ctypes
 import os
 import re
 from dataclasses import dataclass
-from typing import Optional, Sequence, Tuple
+from typing import Optional, Sequence
 
 import numpy as np
 
