@@ -661,11 +661,11 @@ hipError_t launch_probe_copy(const float *Zsrc, int64_t n, float *Zdst, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-// Probe contractions over a block of buffered time steps (Algorithm 1, lines
-// 2 and 6, time-blocked): one thread per physical point and shot keeps RC
-// accumulators in registers while it streams the buffered slots; the probing
-// row Z[s, :] is uniform across the block and is read through scalar loads.
-// Grid (x chunks of 256, ny * nz rows, shots).
+// Probe contractions over a block of buffered time steps (Algorithm 1's
+// forward and back-propagation accumulations, time-blocked): one thread per
+// physical point and shot keeps RC accumulators in registers while it streams
+// the buffered slots; the probing row Z[s, :] is uniform across the block and
+// is read through scalar loads.  Grid (chunks of 256 points, shots).
 // ---------------------------------------------------------------------------
 struct PointIndex {
     int off;     // offset within a shot field
