@@ -144,3 +144,25 @@ def test_objective_workspace_and_null_arguments():
     # J must not be NULL; nothing is launched
     assert L.tpx_objective(ctypes.byref(g), ctypes.byref(ge), 0x1000, 0x2000, None, None, 0x3000, obj,
                            None) == tpx.E_INVAL
+
+
+def test_memory_follows_the_papers_estimates():
+    # Memory estimates section, Table 1: probing keeps r x N values per pass
+    # (u-bar in the forward pass, v-bar in the backward pass, 2 r N in all),
+    # where the stored-history gradient keeps N x n_t
+    grid = tpx.Grid(**GRID)                       # N = 30 x 40, n_t = 100, 5 padding nodes
+    geom = _geom([[100.0, 0, 50.0], [200.0, 0, 50.0]], [[[10.0, 0, 20.0]] * 3] * 2)
+    S, N, N_pad, nt = 2, 30 * 40, 40 * 50, 100
+
+    def a(b):
+        return (b + 255) // 256 * 256
+
+    for r in (4, 8, 16):
+        assert tpx.state_bytes(grid, geom, tpx.Probe(r=r)) == a(S * r * N * 4)
+        keep = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=r, keep_vbar=True))
+        fold = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=r))
+        # v-bar replaces the folded path's one-field partial gradient
+        assert keep - fold == a(S * r * N * 4) - a(S * N * 4)
+    full = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom)
+    fwd = tpx.workspace_bytes(tpx.CALL_FORWARD, grid, geom)
+    assert full - fwd >= (nt - 4) * S * N_pad * 4    # the history: n_t padded fields per shot

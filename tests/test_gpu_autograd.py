@@ -41,7 +41,7 @@ def _loss_and_grad(c, m_np, probe):
 def c2():
     wl = workload("c2_autograd_2d")
     c = Case(wl)
-    c.dobs = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    c.dobs = c.dobs_oracle()   # observed data from the oracle, fed to both sides
     return c
 
 

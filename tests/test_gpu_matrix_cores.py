@@ -18,7 +18,7 @@ if gpu_available():
 
 import oracle  # noqa: E402
 from paper_2104_00794_amd import tpx  # noqa: E402
-from paper_2104_00794_amd.inputs import small_2d, small_3d  # noqa: E402
+from paper_2104_00794_amd.inputs import small_2d, small_3d, workload  # noqa: E402
 
 
 def _print_case(name, **kw):
@@ -115,3 +115,26 @@ def test_split_probes_on_the_matrix_cores_match_oracle(r, keep_vbar, side):
     g_v, _ = _with_option(0, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d))
     assert rel_l2(to_np(g_m), g_o) <= TOL
     assert rel_l2(to_np(g_m), to_np(g_v)) <= 1e-5
+
+
+def test_c1_r64_full_configuration_on_the_matrix_cores():
+    # 801 x 301, 16 shots batched in one launch, order 8, nt = 2401, r = 64
+    # Rademacher under the default option: the accumulation and the fold run on
+    # the matrix cores over 1024-level blocks (the benchmarked r = 64 launch
+    # configuration).  The gradient is compared at 4096 sampled points that the
+    # oracle computes one by one, and the objective in full.
+    _print_case("c1_r64_full")
+    wl = workload("c1_layered_2d_16shots")
+    c = Case(wl)
+    dobs = c.dobs_oracle()
+    r = 64
+    nz, nx = wl.shape
+    pts = np.sort(np.random.default_rng(64).choice(nz * nx, 4096, replace=False))
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=r, seed=wl.probe_seed,
+                                      points=pts)
+    probe = tpx.Probe(r=r, seed=wl.probe_seed)
+    g_g, J_g = _with_option(1, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs)))
+    g_s = to_np(g_g).reshape(-1)[pts]
+    assert np.linalg.norm(g_o) > 0
+    assert rel_l2(g_s, g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
