@@ -156,6 +156,9 @@ def main():
     # the probe contraction
     b_alg_step = (16.0 + 4.0 / S) / 2.0 if wl.ndim == 2 else 12.0 + 4.0 / S
     b_alg_path = b_alg_step + 4.0 * phi
+    # the same path priced one step per pass (12 + 4/S + 4 phi): what an unfused
+    # leapfrog must move, and a looser bound than the fused model above
+    b_alg_one_step = 12.0 + 4.0 / S + 4.0 * phi
 
     # ---- per-kernel durations (HIP events on the launch stream) ----------------------------
     kernels = {}
@@ -219,6 +222,7 @@ def main():
                        "p99": round(float(np.percentile(lat, 99)), 3)},
         "hbm_roofline_pct": round(100.0 * gpts * b_alg_path / HBM_PEAK_GBS, 2),
         "b_alg_bytes_per_point_step": round(b_alg_path, 3),
+        "hbm_roofline_pct_one_step_model": round(100.0 * gpts * b_alg_one_step / HBM_PEAK_GBS, 2),
         "roofline": roofline,
         "kernels": kernels,
         "kernel_timing": "HIP events on the launch stream around each run of consecutive launches of one "
