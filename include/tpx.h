@@ -232,7 +232,8 @@ enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2 };
  * six, the dropped terms below 2^-21 of each product.  Value 0: never; 1: the
  * folded adjoint contraction when r >= 32 and the ubar/vbar accumulations
  * when r >= 64 (where they measured faster than the vector units); 2: every
- * contraction.  Explicit probes must be 16-byte aligned to qualify.  Results
+ * contraction.  Explicit probes must be 16-byte aligned to qualify, and a
+ * ring slot (one level of all shots) must hold fewer than 2^32 floats.  Results
  * agree with the FP32 path to rounding (not bitwise).  Workspace sizes do
  * not depend on this option. */
 tpx_status tpx_set_option(int32_t option, int64_t value);

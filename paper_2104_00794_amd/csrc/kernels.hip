@@ -137,7 +137,7 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
     const int64_t so = shot * L.shot_floats + XO;
     const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cur + so, span), rp = buf_rsrc(a.prev + so, span);
     const __amdgpu_buffer_rsrc_t rb = buf_rsrc(a.beta + XO, span);
-    auto rowoff = [&](int z) { return (uint32_t)((z + R) * G0 * 4); };   // byte offset of padded row z
+    auto rowoff = [&](int z) { return (uint32_t)(z + R) * (uint32_t)G0 * 4u; };   // byte offset of padded row z (< 2^32)
 
     // stage u^k, rows z0 - 2R .. z0 + TZ + 2R - 1, columns x0 - 2R .. x0 + TX + 2R - 1
     const int sx = x0 - 2 * R + lx, sx2 = sx + 64;

@@ -471,9 +471,11 @@ int probe_parts(const tpx_probe *pr) {
 
 enum { MFMA_ACCUM = 1, MFMA_FOLD = 2 };
 
-int mfma_selected(const tpx_probe *pr) {
+int mfma_selected(const Layout &L, const tpx_probe *pr) {
     const int opt = g_mfma.load();
     if (!mfma_eligible(pr) || opt == 0) return 0;
+    // the matrix-core kernels step from ring slot to ring slot with 32-bit strides
+    if (L.slot_floats >= ((int64_t)1 << 32)) return 0;
     // the fold reads the caller's explicit probes as 16-byte vectors
     if (pr->kind == TPX_PROBE_EXPLICIT && ((uintptr_t)pr->Z & 15) != 0) return 0;
     if (opt == 2) return MFMA_ACCUM | MFMA_FOLD;
@@ -1045,7 +1047,7 @@ const float *probe_matrix_dev(Ctx &C, const tpx_probe *pr, const float *d_obs, t
             });
         Zc = Z;
     }
-    const int mm = mfma_selected(pr);
+    const int mm = mfma_selected(C.P.L, pr);
     C.zparts = mfma_eligible(pr) ? probe_parts(pr) : 1;
     if (e == hipSuccess && (mm & MFMA_ACCUM)) {
         void *zpk = C.ws + C.plan.zpk;

@@ -166,3 +166,22 @@ def test_memory_follows_the_papers_estimates():
     full = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom)
     fwd = tpx.workspace_bytes(tpx.CALL_FORWARD, grid, geom)
     assert full - fwd >= (nt - 4) * S * N_pad * 4    # the history: n_t padded fields per shot
+
+
+def test_largest_shot_field_accepted_and_the_next_rejected():
+    # the step kernels address one shot's padded field with 32-bit byte
+    # offsets: fields of 2^30 floats or more are refused on the host
+    geom = _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]])
+    ok = tpx.Grid((31_990, 32_000), h=10.0, dt=1.5, nt=10, order=8, nbl=20, damp_vmax=3.0)
+    # padded rows of 32,040 + 32 + 4 floats (pitch 32,096) by 32,030 + 8 rows
+    assert tpx.workspace_bytes(tpx.CALL_FORWARD, ok, geom) >= 4 * 32_096 * 32_038 * 4
+    big = tpx.Grid((33_000, 33_000), h=10.0, dt=1.5, nt=10, order=8, nbl=20, damp_vmax=3.0)
+    with pytest.raises(tpx.TpxError) as e:
+        tpx.workspace_bytes(tpx.CALL_FORWARD, big, geom)
+    assert "2^30" in str(e.value)
+    # 3D: 900^3 physical nodes fit (992 x 948 x 948 floats padded), 1000^3 do not
+    g3 = dict(h=10.0, dt=1.0, nt=10, order=8, nbl=20, damp_vmax=3.0)
+    geom3 = _geom([[100.0, 100.0, 50.0]], [[[10.0, 10.0, 20.0]]])
+    assert tpx.workspace_bytes(tpx.CALL_FORWARD, tpx.Grid((900, 900, 900), **g3), geom3) >= 3 * 992 * 948 * 948 * 4
+    with pytest.raises(tpx.TpxError):
+        tpx.workspace_bytes(tpx.CALL_FORWARD, tpx.Grid((1000, 1000, 1000), **g3), geom3)

@@ -312,6 +312,62 @@ def test_c3_full_grid_truncated_record():
     assert abs(float(J_g.item()) - J_o) <= TOL * J_o
 
 
+def test_largest_2d_shot_fields():
+    # Two shots of 5,200,000 x 100 nodes: each padded shot field holds 1.0e9
+    # floats (93% of the 2^30 limit), so in-shot byte offsets pass 2^31 and the
+    # second shot starts 4 GB into each ring slot.  Shot 0 sits in interior
+    # (fast-path) tiles, shot 1 in the bottom absorbing layer's tiles; one
+    # receiver lies on the last physical column, one on the bottom-left corner.
+    # A slow block around each source scatters 30% of the traces within the
+    # 8-step record, which keeps the FP64 oracle to about a minute.  The
+    # gradient is compared on the 5,000 nodes around the sources, with the
+    # contractions on the vector units (default at r = 16) and on the matrix
+    # cores.
+    import torch
+    nz, nx, h, nt = 5_200_000, 100, 10.0, 8
+    _print_case("largest_2d", nz=nz, nx=nx, nshots=2, nt=nt)
+    xs, zs = [500.0, 300.0], [(nz - 200) * h, (nz - 30) * h]
+    src = np.array([[x, 0.0, z] for x, z in zip(xs, zs)])
+    rec = np.array([[[x + dx, 0.0, z + dz] for dx, dz in ((-33.0, 27.0), (41.0, -12.5), (0.0, 50.0),
+                                                           (-47.5, -40.0), (12.5, 0.0))] +
+                    [[990.0, 0.0, z + 5.0] if i == 0 else [0.0, 0.0, (nz - 1) * h]]
+                    for i, (x, z) in enumerate(zip(xs, zs))])
+    rng = np.random.default_rng(2)
+    wav = rng.standard_normal((2, nt)).astype(np.float32).astype(np.float64)
+    m_true = np.full((nz, nx), 0.25)
+    for x, z in zip(xs, zs):
+        r0, c0 = int(z / h), int(x / h)
+        m_true[r0 - 6:r0 + 7, c0 - 10:c0 + 11] = 0.3125
+    m0 = np.full((nz, nx), 0.25)
+    og = oracle.Grid((nz, nx), h=h, dt=1.5, nt=nt, order=8, nbl=20, damp_vmax=3.0)
+    tg = tpx.Grid((nz, nx), h=h, dt=1.5, nt=nt, order=8, nbl=20, damp_vmax=3.0)
+    geom = tpx.Geometry(src, rec, cuda(wav))
+    dobs = oracle.forward(og, m_true, src, rec, wav).astype(np.float32).astype(np.float64)
+    d_g = to_np(tpx.forward(tg, geom, cuda(m_true)))
+    del m_true
+    assert rel_l2(d_g, dobs) <= TOL
+    pts = np.concatenate([np.arange((int(z / h) - 12) * nx, (int(z / h) + 13) * nx) for z in zs])
+    g_o, J_o = oracle.gradient_probed(og, m0, src, rec, wav, dobs, r=16, seed=9, points=pts)
+    assert np.linalg.norm(g_o) > 0 and J_o > 1e-3 * 0.5 * float(np.sum(dobs ** 2))
+    probe = tpx.Probe(r=16, seed=9)
+    m0_d, dobs_d = cuda(m0), cuda(dobs)
+    del m0
+    ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_PROBED, tg, geom, probe)
+    sel = torch.as_tensor(pts, device="cuda")
+    for option in (1, 2):
+        old = tpx.get_option(tpx.OPT_MATRIX_CORES)
+        try:
+            tpx.set_option(tpx.OPT_MATRIX_CORES, option)
+            g_g, J_g = tpx.gradient_probed(tg, geom, probe, m0_d, dobs_d, ws=ws)
+        finally:
+            tpx.set_option(tpx.OPT_MATRIX_CORES, old)
+        g_s = g_g.reshape(-1).index_select(0, sel).double().cpu().numpy()
+        del g_g
+        print("[largest_2d] option", option, "rel", rel_l2(g_s, g_o), flush=True)
+        assert rel_l2(g_s, g_o) <= TOL
+        assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
 def test_overlapped_contractions_are_bitwise_identical():
     # contractions on the auxiliary stream (ring of 2b + 3 slots) give the same
     # bits as in stream order: same kernels, same summation order
