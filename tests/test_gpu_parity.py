@@ -368,6 +368,41 @@ def test_largest_2d_shot_fields():
         assert abs(float(J_g.item()) - J_o) <= TOL * J_o
 
 
+def test_largest_3d_shot_field():
+    # One shot of 100,000 x 30 x 30 nodes: the padded field holds 1.0e9 floats
+    # (128 x 78 x 100,048, 93% of the 2^30 limit), so plane offsets pass 2^31
+    # bytes; the source sits 100 planes above the bottom, inside a slow block.
+    import torch
+    nz, ny, nx, h, nt = 100_000, 30, 30, 10.0, 8
+    _print_case("largest_3d", nz=nz, ny=ny, nx=nx, nt=nt)
+    x, y, z = 150.0, 145.0, (nz - 100) * h
+    src = np.array([[x, y, z]])
+    rec = np.array([[[x + dx, y + dy, z + dz] for dx, dy, dz in ((-33.0, 12.5, 27.0), (41.0, 0.0, -12.5),
+                                                                  (0.0, -20.0, 45.0), (12.5, 7.5, 0.0))] +
+                    [[290.0, 290.0, (nz - 1) * h]]])
+    rng = np.random.default_rng(3)
+    wav = rng.standard_normal((1, nt)).astype(np.float32).astype(np.float64)
+    m_true = np.full((nz, ny, nx), 0.25)
+    r0, c0, y0 = int(z / h), int(x / h), int(y / h)
+    m_true[r0 - 5:r0 + 6, y0 - 5:y0 + 6, c0 - 5:c0 + 6] = 0.3125
+    m0 = np.full((nz, ny, nx), 0.25)
+    og = oracle.Grid((nz, ny, nx), h=h, dt=1.0, nt=nt, order=8, nbl=20, damp_vmax=3.0)
+    tg = tpx.Grid((nz, ny, nx), h=h, dt=1.0, nt=nt, order=8, nbl=20, damp_vmax=3.0)
+    geom = tpx.Geometry(src, rec, cuda(wav))
+    dobs = oracle.forward(og, m_true, src, rec, wav).astype(np.float32).astype(np.float64)
+    d_g = to_np(tpx.forward(tg, geom, cuda(m_true)))
+    del m_true
+    assert rel_l2(d_g, dobs) <= TOL
+    pts = np.arange((r0 - 8) * ny * nx, (r0 + 9) * ny * nx)
+    g_o, J_o = oracle.gradient_probed(og, m0, src, rec, wav, dobs, r=16, seed=11, points=pts)
+    assert np.linalg.norm(g_o) > 0 and J_o > 1e-3 * 0.5 * float(np.sum(dobs ** 2))
+    g_g, J_g = tpx.gradient_probed(tg, geom, tpx.Probe(r=16, seed=11), cuda(m0), cuda(dobs))
+    g_s = g_g.reshape(-1).index_select(0, torch.as_tensor(pts, device="cuda")).double().cpu().numpy()
+    print("[largest_3d] rel", rel_l2(g_s, g_o), flush=True)
+    assert rel_l2(g_s, g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
 def test_overlapped_contractions_are_bitwise_identical():
     # contractions on the auxiliary stream (ring of 2b + 3 slots) give the same
     # bits as in stream order: same kernels, same summation order
