@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--probe", default=None, help="rademacher | gauss_b64 | range_finder")
     ap.add_argument("--block", type=int, default=0, help="time steps per probe contraction (0 = default)")
     ap.add_argument("--keep-vbar", action="store_true", help="accumulate vbar instead of folding it")
+    ap.add_argument("--dtt-side", type=int, default=0, choices=[0, 1],
+                    help="1: probe the second time difference of u and lambda itself (Algorithm 1 as printed)")
+    ap.add_argument("--imaging", type=int, default=0, choices=[0, 1],
+                    help="1: image the probed fields through their spatial gradients (Eq. 5; keeps vbar)")
     ap.add_argument("--overlap", action="store_true",
                     help="run the probe contractions on the auxiliary stream, overlapping the next time block")
     ap.add_argument("--matrix-cores", type=int, default=None, choices=[0, 1, 2],
@@ -111,7 +115,10 @@ def main():
     geom = tpx.Geometry(wl.src_pos(), wl.rec_pos(), wav)
     m_true = torch.tensor(mt, dtype=torch.float32, device=dev)
     m_0 = torch.tensor(m0, dtype=torch.float32, device=dev)
-    probe = tpx.Probe(kind=kind, r=r, seed=wl.probe_seed, block=args.block, keep_vbar=args.keep_vbar)
+    if args.imaging:
+        args.keep_vbar = True
+    probe = tpx.Probe(kind=kind, r=r, seed=wl.probe_seed, block=args.block, keep_vbar=args.keep_vbar,
+                      dtt_side=args.dtt_side, imaging=args.imaging)
 
     d_obs = tpx.forward(grid, geom, m_true)           # synthetic observed data (untimed input)
     ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_PROBED, grid, geom, probe, dev)
@@ -214,6 +221,7 @@ def main():
         "config": {"workload": wl.name, "grid": "x".join(str(s) for s in wl.shape[::-1]), "h_m": wl.h,
                    "space_order": wl.order, "shots": S, "nt": nt, "nbl": wl.nbl, "r": r, "probe": kind,
                    "block": args.block or "default", "keep_vbar": bool(args.keep_vbar),
+                   "dtt_side": args.dtt_side, "imaging": args.imaging,
                    "overlap_contractions": bool(tpx.get_option(tpx.OPT_OVERLAP_CONTRACTIONS)),
                    "matrix_core_contractions": matrix_core_use(kind, r, bool(args.keep_vbar)),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
