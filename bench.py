@@ -197,6 +197,11 @@ def main():
                         "k_step3d<R=%d>" % R,
                         "bytes_per_launch": bytes_per_launch, "avg_launch_us": st["avg_us"]}
 
+    # ---- reference rate: a plain device copy of 1 GiB (after the timed region) ------------
+    copy_gbps = None
+    if not args.no_profile_pass:
+        copy_gbps = copy_bandwidth(dev)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -232,6 +237,7 @@ def main():
         "b_alg_bytes_per_point_step": round(b_alg_path, 3),
         "hbm_roofline_pct_one_step_model": round(100.0 * gpts * b_alg_one_step / HBM_PEAK_GBS, 2),
         "roofline": roofline,
+        "copy_GBps": copy_gbps,
         "kernels": kernels,
         "kernel_timing": "HIP events on the launch stream around each run of consecutive launches of one "
                          "kernel kind, in one profiled call after the timed region",
@@ -323,6 +329,25 @@ def cpu_baseline(wl, r, kind, nt_sample, shots):
             "seconds": round(dt, 2),
             "sample": "%d of %d shots, first %d of %d time steps, r=%d %s, same grid; FP64 C oracle with OpenMP"
                       % (sample.nshots, wl.nshots, sample.nt, wl.nt, r, kind)}
+
+
+def copy_bandwidth(dev, n: int = 1 << 28, reps: int = 5) -> float:
+    """Read + write bytes per second of a plain 1 GiB device copy (median of `reps`), GB/s:
+    the rate a pure streaming kernel reaches on this HBM."""
+    import torch
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return round(2.0 * 4 * n / float(np.median(times)) / 1e9, 1)
 
 
 def matrix_core_use(kind: str, r: int, keep_vbar: bool) -> str:
