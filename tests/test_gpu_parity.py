@@ -165,6 +165,28 @@ def test_probed_gradient_probe_counts(r):
     assert rel_l2(to_np(g_g), g_o) <= TOL
 
 
+@pytest.mark.parametrize("ndim,r,block,mfma", [(2, 1, 1, 1), (2, 3, 149, 1), (2, 5, 2, 1), (2, 16, 1, 2),
+                                               (2, 32, 3, 2), (3, 1, 1, 1), (3, 16, 2, 2)])
+def test_probed_gradient_degenerate_blocks(ndim, r, block, mfma):
+    # one probe; one buffered level per contraction block (a 3-slot ring);
+    # one block for the whole record; 16-level matrix-core tiles holding 1-3
+    # live levels
+    _print_case("grad_blocks", ndim=ndim, r=r, block=block, mfma=mfma)
+    c = Case(small_2d(nz=30, nx=90, nt=150, nshots=2, nrec=11) if ndim == 2 else
+             small_3d(nz=20, ny=12, nx=30, nt=60, nshots=2, nrec=7))
+    dobs = c.dobs_oracle()
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=r, seed=21)
+    old = tpx.get_option(tpx.OPT_MATRIX_CORES)
+    try:
+        tpx.set_option(tpx.OPT_MATRIX_CORES, mfma)
+        g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=r, seed=21, block=block), cuda(c.m0),
+                                       cuda(dobs))
+    finally:
+        tpx.set_option(tpx.OPT_MATRIX_CORES, old)
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
 def test_identity_and_orthonormal_probes_give_exact_gradient():
     c = Case(small_2d(nz=30, nx=70, nt=120, nshots=2, nrec=9))
     dobs = c.dobs_oracle()
