@@ -343,7 +343,7 @@ int orc_probe_matrix(int32_t kind, int32_t r, uint64_t seed, int32_t nt, int32_t
  * injects q^k and produces u^{k+1}; the trace is d^k = R u^k for k = 0..nt-1.
  * Optional outputs: u_hist[k][phys] = u^k on the physical region (k = 0..nt-1),
  * ubar[j][pt] += Z[s][j] u^s (s = 1..nt-1) at the listed physical points
- * (Algorithm 1, forward loop; spec side: the wavefield itself is probed),
+ * (Algorithm 1, forward loop; the default side: the wavefield itself is probed),
  * ubar2[j][pt] += Z[k][j] (u^{k+1} - 2u^k + u^{k-1}) (k = 0..nt-2; the paper's
  * Algorithm 1 side, second time difference probed in the forward loop). */
 typedef struct {
@@ -415,7 +415,7 @@ done:
  *   q_adj[k] = dt^2 S lambda^k  (k = 0..nt-1; zero at k = nt-1),
  *   lam_hist[k][phys] = lambda^k (optional),
  *   vbar[j][pt] += Z[s][j] w^s, w^s = lambda^{s-1} - 2 lambda^s + lambda^{s+1},
- *                  s = 1..nt-1  (spec side),
+ *                  s = 1..nt-1  (the default side),
  *   vbar2[j][pt] += Z[k][j] lambda^k, k = 0..nt-2  (the paper's side). */
 typedef struct {
     double *lam_hist;
