@@ -370,8 +370,9 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
     const bool oa = FAST || (x < P0 && ya < P1), ob = FAST || (x < P0 && yb < P1);   // columns inside the box
     const uint32_t va = lane(ya, x), vb = lane(yb, x);
 
-    // halo of a plane: rows ly and ly + 12 (y0 - R + ly, y0 + 8 + ly), all 72 columns;
-    // rows 4 + ly and 8 + ly (the centre rows) only their x-halo columns.
+    // halo of a plane: staged rows ly and T3Y + R + ly (y0 - R + ly, y0 + T3Y + ly) for
+    // ly < R, all 64 + 2R columns; the centre rows R + ly and R + 4 + ly only their
+    // x-halo columns.
     const int hy0 = y0 - R + ly, hy1 = y0 + T3Y + ly;
     const int hxa = x0 - R + lx;                     // columns 0..63 of the staged row
     const int hxb = x0 - R + 64 + lx;                // columns 64..71 (lanes < 2R)
@@ -435,10 +436,12 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
         const float pa = oa ? np[0] : 0.0f, pb = ob ? np[1] : 0.0f, ba = oa ? nbt[0] : 0.0f, bb = ob ? nbt[1] : 0.0f;
 
         float(*pt)[W] = plane_t[lz & 1];
-        pt[ly][lx] = h[0];
-        if (lx < 2 * R) pt[ly][64 + lx] = h[1];
-        pt[T3Y + R + ly][lx] = h[2];
-        if (lx < 2 * R) pt[T3Y + R + ly][64 + lx] = h[3];
+        if (R >= 4 || ly < R) {   // the R halo rows on each side: one per wave when R = 4
+            pt[ly][lx] = h[0];
+            if (lx < 2 * R) pt[ly][64 + lx] = h[1];
+            pt[T3Y + R + ly][lx] = h[2];
+            if (lx < 2 * R) pt[T3Y + R + ly][64 + lx] = h[3];
+        }
         pt[R + ly][R + lx] = qa[R];
         pt[R + 4 + ly][R + lx] = qb[R];
         if (lx < 2 * R) {
