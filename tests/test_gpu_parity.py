@@ -220,6 +220,48 @@ def test_fourth_order_stencil_paths(ndim):
     assert np.array_equal(runs[0], runs[1]) and np.array_equal(runs[0], runs[2])
 
 
+def _check_all_paths(c, r=16, seed=31):
+    d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
+    d_g = to_np(tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true)))
+    assert rel_l2(d_g, d_o) <= TOL
+    dobs = d_o.astype(np.float32).astype(np.float64)
+    g_o, J_o = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    g_g, J_g = tpx.gradient_full(c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=r, seed=seed)
+    for mfma in (1, 2):
+        old = tpx.get_option(tpx.OPT_MATRIX_CORES)
+        try:
+            tpx.set_option(tpx.OPT_MATRIX_CORES, mfma)
+            g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=r, seed=seed, block=23), cuda(c.m0),
+                                           cuda(dobs))
+        finally:
+            tpx.set_option(tpx.OPT_MATRIX_CORES, old)
+        assert rel_l2(to_np(g_g), g_o) <= TOL
+        assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_no_absorbing_layer(ndim):
+    # nbl = 0: the padded box is the physical grid, zero outside, no damping
+    _print_case("nbl0", ndim=ndim)
+    _check_all_paths(Case(small_2d(nz=30, nx=70, nt=150, nbl=0, nshots=2, nrec=9) if ndim == 2 else
+                          small_3d(nz=20, ny=12, nx=30, nt=60, nbl=0, nshots=2, nrec=6)))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_grids_smaller_than_one_tile(ndim):
+    _print_case("tiny", ndim=ndim)
+    _check_all_paths(Case(small_2d(nz=6, nx=7, nt=60, nbl=2, nshots=2, nrec=3) if ndim == 2 else
+                          small_3d(nz=5, ny=4, nx=6, nt=40, nbl=2, nshots=2, nrec=3)))
+
+
+def test_24_shots_in_one_batch():
+    # 24 shots: three shots per XCD group share each tile's beta
+    _print_case("shots24")
+    _check_all_paths(Case(small_2d(nz=30, nx=60, nt=120, nshots=24, nrec=7)))
+
+
 def test_identity_and_orthonormal_probes_give_exact_gradient():
     c = Case(small_2d(nz=30, nx=70, nt=120, nshots=2, nrec=9))
     dobs = c.dobs_oracle()
