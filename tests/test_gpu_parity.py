@@ -637,6 +637,30 @@ def test_range_finder_probes_match_oracle(ndim):
         assert torch.equal(g_split, g_g)
 
 
+@pytest.mark.parametrize("r", [16, 64])
+def test_range_finder_probes_at_large_r(r):
+    # Eq. 6 with many probes: 70 receivers of random observed traces (full rank)
+    # over 1200 samples, so Q is well determined; the tall-skinny QR runs over 9
+    # panels (r = 16) or 4 (r = 64), and the gradient's contractions with Q run
+    # on the matrix cores (split probes)
+    _print_case("range_finder_large_r", r=r)
+    import torch
+    c = Case(small_2d(nz=30, nx=80, nt=1200, nshots=2, nrec=70))
+    dobs = np.random.default_rng(r).standard_normal((2, 1200, 70)).astype(np.float32).astype(np.float64)
+    Qo = oracle.range_finder_probes(dobs, r, 23)
+    probe = tpx.Probe(kind="range_finder", r=r, seed=23)
+    Qg = to_np(tpx.range_finder_probes(c.tgrid(), c.tgeom(), probe, cuda(dobs)))
+    for s in range(2):
+        assert np.abs(Qg[s].T @ Qg[s] - np.eye(r)).max() <= 1e-5
+        assert np.linalg.norm(Qg[s] @ Qg[s].T - Qo[s] @ Qo[s].T) <= 1e-5 * np.sqrt(r)
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, kind="explicit", r=r, Z=Qo,
+                                      scale=1.0)
+    g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
+    assert rel_l2(to_np(g_g), g_o) <= TOL
+    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+    assert torch.isfinite(g_g).all()
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_gradient_imaging_condition_matches_oracle(ndim):
     # Eq. 5: the space-only operator grad applied to the r probed fields
