@@ -138,3 +138,23 @@ def test_c1_r64_full_configuration_on_the_matrix_cores():
     assert np.linalg.norm(g_o) > 0
     assert rel_l2(g_s, g_o) <= TOL
     assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+
+
+def test_identity_probes_and_gradient_imaging_on_the_matrix_cores():
+    # identity probes with r = nt = 128 (eight 16-level tiles, exact in
+    # bfloat16) give the exact gradient; Eq. 5's imaging of vbar accumulated on
+    # the matrix cores matches the oracle in 2D and 3D
+    _print_case("mfma_identity_imaging")
+    c = Case(small_2d(nz=30, nx=70, nt=128, nshots=2, nrec=9))
+    dobs = c.dobs_oracle()
+    g_full, _ = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    g_id, _ = _with_option(2, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(kind="identity", r=128),
+                                                         cuda(c.m0), cuda(dobs)))
+    assert rel_l2(to_np(g_id), g_full) <= TOL
+    for ndim in (2, 3):
+        c = _case(ndim)
+        dobs = c.dobs_oracle()
+        g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=16, seed=3, imaging=1)
+        probe = tpx.Probe(r=16, seed=3, block=37, keep_vbar=True, imaging=1)
+        g_g, _ = _with_option(2, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs)))
+        assert rel_l2(to_np(g_g), g_o) <= TOL
