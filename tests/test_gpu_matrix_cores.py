@@ -158,3 +158,27 @@ def test_identity_probes_and_gradient_imaging_on_the_matrix_cores():
         probe = tpx.Probe(r=16, seed=3, block=37, keep_vbar=True, imaging=1)
         g_g, _ = _with_option(2, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs)))
         assert rel_l2(to_np(g_g), g_o) <= TOL
+
+
+def test_misaligned_explicit_probes_fall_back_to_the_vector_units():
+    # the matrix-core fold reads explicit probes as 16-byte vectors: a Z that
+    # starts 4 bytes into its allocation takes the vector-unit contractions
+    import torch
+    _print_case("mfma_misaligned_Z")
+    c = Case(small_2d(nz=30, nx=70, nt=100, nshots=2, nrec=9))
+    dobs = c.dobs_oracle()
+    r = 32
+    Z = np.random.default_rng(5).standard_normal((2, 100, r)).astype(np.float32).astype(np.float64)
+    buf = torch.zeros(Z.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = cuda(Z).reshape(-1)
+    Zmis = buf[1:].view(2, 100, r)
+    assert Zmis.data_ptr() % 16 != 0
+    g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, kind="explicit", r=r, Z=Z,
+                                    scale=1.0 / r)
+    m, d = cuda(c.m0), cuda(dobs)
+    for Zt in (cuda(Z), Zmis):
+        probe = tpx.Probe(kind="explicit", r=r, Z=Zt, scale=1.0 / r, block=37)
+        g_m, _ = _with_option(2, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d))
+        assert rel_l2(to_np(g_m), g_o) <= TOL
+    g_v, _ = _with_option(0, lambda: tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d))
+    assert torch.equal(g_m, g_v)   # the misaligned call ran the vector-unit kernels
