@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--max-active", type=int, default=4,
                     help="jobs the server keeps on the GPU at once (default: one per hardware queue)")
     ap.add_argument("--inflight", type=int, default=2, help="chunks each served job keeps queued")
+    ap.add_argument("--large-points", type=float, default=3e6,
+                    help="padded points over a job's shots from which it counts as large")
+    ap.add_argument("--max-large", type=int, default=1, help="large jobs the server runs at once")
     return ap.parse_args()
 
 
@@ -264,6 +267,7 @@ def serving(args, dev):
         reqs.append(serve.Request(i, grid, geom, tpx.Probe(r=wl.r, seed=wl.probe_seed, block=256),
                                   torch.tensor(m0, dtype=torch.float32, device=dev), d_obs))
     torch.cuda.synchronize()
+    print("serving: %d requests prepared" % len(reqs), file=sys.stderr, flush=True)
     # service time of the plain path (also the warm-up), then the arrival rate
     svc = serve.run_sequential(reqs)
     mean_service = float(np.mean([r.finished - r.admitted for r in svc.values()]))
@@ -272,8 +276,10 @@ def serving(args, dev):
     for q, a in zip(reqs, arr):
         q.arrival = float(a)
     seq = serve.run_sequential(reqs)
+    print("serving: plain path on the Poisson trace done", file=sys.stderr, flush=True)
     srv = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=args.chunk_steps,
-                       max_active=args.max_active, nstreams=8, inflight=args.inflight)
+                       max_active=args.max_active, nstreams=8, inflight=args.inflight,
+                       large_points=args.large_points, max_large=args.max_large)
     bat = srv.run(reqs)
     same = all(torch.equal(seq[q.rid].g, bat[q.rid].g) for q in reqs if bat[q.rid].status == "ok")
     a, b = serve.summarize(seq, reqs), serve.summarize(bat, reqs)
@@ -282,9 +288,12 @@ def serving(args, dev):
     # of the 256 CUs idle)
     for q in reqs:
         q.arrival = 0.0
+    print("serving: server on the Poisson trace done", file=sys.stderr, flush=True)
     sat_seq = serve.summarize(serve.run_sequential(reqs), reqs)
+    print("serving: plain path at saturation done", file=sys.stderr, flush=True)
     srv2 = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=args.chunk_steps,
-                        max_active=args.max_active, nstreams=8, inflight=args.inflight)
+                        max_active=args.max_active, nstreams=8, inflight=args.inflight,
+                        large_points=args.large_points, max_large=args.max_large)
     sat_bat = serve.summarize(srv2.run(reqs), reqs)
     out = {
         "metric": "serving: gradient p50/p99 latency and aggregate GPts/s, continuous batching vs one-at-a-time",
@@ -294,7 +303,8 @@ def serving(args, dev):
                                "r in {8,32,64}, order 8", "requests": len(reqs),
                    "arrival": "Poisson, %.2f req/s = 0.8 x sequential service rate" % rate,
                    "hbm_budget_gb": args.budget_gb, "chunk_steps": args.chunk_steps,
-                   "max_active": args.max_active, "inflight": args.inflight},
+                   "max_active": args.max_active, "inflight": args.inflight,
+                   "large_points": args.large_points, "max_large": args.max_large},
         "batched": b, "sequential": a, "mean_service_ms": round(1e3 * mean_service, 2),
         "saturated": {"batched": sat_bat, "sequential": sat_seq,
                       "throughput_ratio": round(sat_bat["gpts_per_s"] / sat_seq["gpts_per_s"], 3)},

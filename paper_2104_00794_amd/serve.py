@@ -76,10 +76,19 @@ class Server:
     """max_active defaults to 4, the number of hardware queues HIP gives a
     process here (GPU_MAX_HW_QUEUES): more concurrent jobs share queues and
     caches, and the measured saturated throughput drops below the sequential
-    path's."""
+    path's.
+
+    A job whose levels hold at least `large_points` padded grid points over all
+    its shots fills the GPU with one step launch by itself; at most `max_large`
+    such jobs run at once (two of them only slow each other down), while
+    smaller jobs fill the gaps around them.  Waiting requests are admitted in
+    arrival order, a blocked large request letting smaller ones behind it
+    pass."""
 
     def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 128, max_active: int = 4,
-                 nstreams: int = 8, inflight: int = 2, device=None):
+                 nstreams: int = 8, inflight: int = 2, device=None, large_points: float = 3e6, max_large: int = 1):
+        self.large_points = float(large_points)
+        self.max_large = int(max_large)
         self.budget = float(hbm_budget_bytes)
         self.chunk = int(chunk_steps)
         self.max_active = int(max_active)
@@ -87,6 +96,7 @@ class Server:
         self.device = torch.device(device or "cuda")
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(nstreams)]
         self.peak_active = 0
+        self.peak_large = 0
         self.peak_bytes = 0
         self.in_use_bytes = 0   # workspace bytes still held when run() returns
 
@@ -97,6 +107,7 @@ class Server:
         active: List[_Active] = []
         free_streams = list(self.streams)
         used = 0
+        wsb: Dict[int, int] = {}   # workspace bytes per request (sizing builds the tables: done once)
         results: Dict[int, Result] = {}
         t0 = time.perf_counter()
         while pend or waiting or active:
@@ -115,26 +126,36 @@ class Server:
                 if not st.cancelled and st.req.cancel_at is not None and st.req.cancel_at <= now:
                     st.cancelled = True
                     results[st.req.rid].status = "cancelled"
-            # admission at chunk boundaries, first come first served
-            while waiting and len(active) < self.max_active and free_streams:
-                req = waiting[0]
-                need = req.workspace_bytes() + 4 * int(np.prod(req.grid.shape)) + 8
+            # admission at chunk boundaries, in arrival order; a large request
+            # blocked by a running large job lets smaller ones pass
+            nlarge = sum(1 for st in active if self._large(st.req))
+            for req in list(waiting):
+                if len(active) >= self.max_active or not free_streams:
+                    break
+                if req.rid not in wsb:
+                    wsb[req.rid] = req.workspace_bytes()
+                need = wsb[req.rid] + 4 * int(np.prod(req.grid.shape)) + 8
                 if need > self.budget:
-                    waiting.popleft()
+                    waiting.remove(req)
                     results[req.rid].status = "rejected: workspace exceeds the HBM budget"
                     results[req.rid].finished = now
                     continue
+                large = self._large(req)
+                if large and nlarge >= self.max_large:
+                    continue
                 if used + need > self.budget:
                     break
-                waiting.popleft()
+                waiting.remove(req)
+                nlarge += 1 if large else 0
                 stream = free_streams.pop()
                 with torch.cuda.stream(stream):
-                    ws = torch.empty(req.workspace_bytes(), dtype=torch.uint8, device=self.device)
+                    ws = torch.empty(wsb[req.rid], dtype=torch.uint8, device=self.device)
                     job = tpx.Job(req.grid, req.geom, req.probe, req.m, req.d_obs, ws=ws, stream=stream)
                 active.append(_Active(req, job, stream, need, now))
                 results[req.rid].admitted = now
                 used += need
                 self.peak_active = max(self.peak_active, len(active))
+                self.peak_large = max(self.peak_large, nlarge)
                 self.peak_bytes = max(self.peak_bytes, used)
             # advance every active job by one chunk, keeping a bounded queue per job
             for st in list(active):
@@ -164,6 +185,11 @@ class Server:
         torch.cuda.synchronize(self.device)
         self.in_use_bytes = used
         return results
+
+
+    def _large(self, req: Request) -> bool:
+        npad = int(np.prod([n + 2 * req.grid.nbl for n in req.grid.shape]))
+        return req.geom.nshots * npad >= self.large_points
 
 
 def run_sequential(requests: List[Request], device=None) -> Dict[int, Result]:

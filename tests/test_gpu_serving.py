@@ -57,6 +57,22 @@ def test_results_identical_alone_and_in_the_mix():
     assert s["completed"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
 
 
+def test_one_large_job_at_a_time():
+    # with the large-job threshold at the median job size, at most one large
+    # job runs while small ones pass it; results stay bitwise those of the
+    # plain path
+    reqs = [make_request(i) for i in range(10)]
+    sizes = sorted(q.geom.nshots * int(np.prod([n + 2 * q.grid.nbl for n in q.grid.shape])) for q in reqs)
+    alone = serve.run_sequential(reqs)
+    srv = serve.Server(hbm_budget_bytes=50e9, chunk_steps=32, max_active=4, nstreams=6,
+                       large_points=sizes[len(sizes) // 2], max_large=1)
+    mixed = srv.run(reqs)
+    assert srv.peak_large == 1 and srv.peak_active > 1
+    for r in reqs:
+        assert mixed[r.rid].status == "ok"
+        assert torch.equal(alone[r.rid].g, mixed[r.rid].g), r.rid
+
+
 def test_admission_by_hbm_budget():
     reqs = [make_request(i, arrival=0.0) for i in range(4)]
     need = [r.workspace_bytes() for r in reqs]
