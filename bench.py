@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--inflight", type=int, default=2, help="chunks each served job keeps queued")
     ap.add_argument("--large-points", type=float, default=3e6,
                     help="padded points over a job's shots from which it counts as large")
-    ap.add_argument("--max-large", type=int, default=1, help="large jobs the server runs at once")
+    ap.add_argument("--max-large", type=int, default=2, help="large jobs the server runs at once")
     return ap.parse_args()
 
 

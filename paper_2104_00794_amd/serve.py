@@ -80,13 +80,13 @@ class Server:
 
     A job whose levels hold at least `large_points` padded grid points over all
     its shots fills the GPU with one step launch by itself; at most `max_large`
-    such jobs run at once (two of them only slow each other down), while
-    smaller jobs fill the gaps around them.  Waiting requests are admitted in
-    arrival order, a blocked large request letting smaller ones behind it
-    pass."""
+    such jobs run at once (two interleave well, four slow each other down),
+    while smaller jobs fill the gaps around them.  Waiting requests are
+    admitted in arrival order, a blocked large request letting smaller ones
+    behind it pass."""
 
     def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 128, max_active: int = 4,
-                 nstreams: int = 8, inflight: int = 2, device=None, large_points: float = 3e6, max_large: int = 1):
+                 nstreams: int = 8, inflight: int = 2, device=None, large_points: float = 3e6, max_large: int = 2):
         self.large_points = float(large_points)
         self.max_large = int(max_large)
         self.budget = float(hbm_budget_bytes)
