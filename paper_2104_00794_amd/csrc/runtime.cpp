@@ -51,7 +51,7 @@ struct ProfRec {
 // between the kernels of a run.
 struct Profiler {
     std::mutex mu;
-    bool on = false;
+    std::atomic<bool> on{false};   // read without the lock on every launch
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     std::vector<ProfRec> recs;

@@ -289,6 +289,46 @@ def test_split_forward_backward_equals_gradient_call():
     assert np.array_equal(to_np(g1), to_np(g2))
 
 
+def test_concurrent_host_threads():
+    # four host threads, each with its own stream, problem and workspace, call
+    # the library at once (ctypes releases the GIL); every result equals the
+    # single-threaded one bit for bit
+    import threading
+    import torch
+    _print_case("threads")
+    cases = [Case(small_2d(nz=30, nx=60 + 10 * i, nt=120, nshots=2, nrec=7, seed=40 + i)) for i in range(2)] + \
+            [Case(small_3d(nz=16, ny=10, nx=24 + 6 * i, nt=50, nshots=1, nrec=5, seed=50 + i)) for i in range(2)]
+    inputs = [(c, cuda(c.m0), cuda(c.dobs_oracle()), tpx.Probe(r=16 * (1 + i % 2), seed=i, block=17))
+              for i, c in enumerate(cases)]
+    ref = [tpx.gradient_probed(c.tgrid(), c.tgeom(), p, m, d) for c, m, d, p in inputs]
+    torch.cuda.synchronize()
+    out = [None] * len(inputs)
+    errors = []
+
+    def work(i):
+        try:
+            c, m, d, p = inputs[i]
+            s = torch.cuda.Stream()
+            res = []
+            for _ in range(3):
+                with torch.cuda.stream(s):
+                    res.append(tpx.gradient_probed(c.tgrid(), c.tgeom(), p, m, d, stream=s))
+            s.synchronize()
+            out[i] = res
+        except Exception as e:   # reported below, on the test's thread
+            errors.append(e)
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(inputs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errors, errors
+    for i, res in enumerate(out):
+        for g, J in res:
+            assert torch.equal(g, ref[i][0]) and torch.equal(J, ref[i][1]), i
+
+
 def test_deterministic_bitwise():
     c = _grad_case(2)
     dobs = c.dobs_oracle()
