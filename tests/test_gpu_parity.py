@@ -166,11 +166,12 @@ def test_probed_gradient_probe_counts(r):
 
 
 @pytest.mark.parametrize("ndim,r,block,mfma", [(2, 1, 1, 1), (2, 3, 149, 1), (2, 5, 2, 1), (2, 16, 1, 2),
-                                               (2, 32, 3, 2), (3, 1, 1, 1), (3, 16, 2, 2)])
+                                               (2, 32, 3, 2), (3, 1, 1, 1), (3, 16, 2, 2), (2, 160, 0, 1),
+                                               (2, 150, 0, 1), (3, 96, 0, 1)])
 def test_probed_gradient_degenerate_blocks(ndim, r, block, mfma):
     # one probe; one buffered level per contraction block (a 3-slot ring);
     # one block for the whole record; 16-level matrix-core tiles holding 1-3
-    # live levels
+    # live levels; more probes than time samples (r > nt)
     _print_case("grad_blocks", ndim=ndim, r=r, block=block, mfma=mfma)
     c = Case(small_2d(nz=30, nx=90, nt=150, nshots=2, nrec=11) if ndim == 2 else
              small_3d(nz=20, ny=12, nx=30, nt=60, nshots=2, nrec=7))
