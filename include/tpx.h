@@ -44,7 +44,11 @@
  * owned by the library and uploads them into the workspace asynchronously, on
  * the same stream; it never waits for the stream.
  * Two calls may run concurrently on different streams if their workspaces
- * and outputs do not overlap.  No C++ exception crosses this boundary.
+ * and outputs do not overlap.  A call may be captured into a HIP graph (stream
+ * capture in relaxed mode; the contraction overlap option off): the tables it
+ * uploads during capture get pinned host copies that the library keeps for
+ * the life of the process, so every replay reads them.  No C++ exception
+ * crosses this boundary.
  */
 #ifndef TPX_H
 #define TPX_H

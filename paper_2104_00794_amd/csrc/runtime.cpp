@@ -644,8 +644,24 @@ struct Staging {
 std::mutex g_stage_mu;
 std::vector<Staging> g_stage;
 
+// Pinned copies of tables uploaded while the stream was being captured into a
+// HIP graph: every replay of the graph reads them again, so they are never
+// reused or freed.
+std::vector<void *> g_captured_tables;
+
 hipError_t upload_async(void *dst, const void *src, size_t n, hipStream_t stream) {
     std::lock_guard<std::mutex> lk(g_stage_mu);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t ec = hipStreamIsCapturing(stream, &cs);
+    if (ec != hipSuccess) return ec;
+    if (cs != hipStreamCaptureStatusNone) {
+        void *h = nullptr;
+        ec = hipHostMalloc(&h, n, hipHostMallocDefault);
+        if (ec != hipSuccess) return ec;
+        memcpy(h, src, n);
+        g_captured_tables.push_back(h);
+        return hipMemcpyAsync(dst, h, n, hipMemcpyHostToDevice, stream);
+    }
     Staging *use = nullptr;
     for (Staging &st : g_stage) {
         if (hipEventQuery(st.done) != hipSuccess) continue;   // copy still pending
