@@ -100,7 +100,8 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uin
 // ---------------------------------------------------------------------------
 // 2D leapfrog steps, one or two per launch.
 //
-// A block owns a tile of T2Z rows by TX = 64 - 2R columns; lane l of each wave
+// A block owns a tile of TZ rows (T2Z, or T2Z_SMALL when a launch would give
+// the CUs fewer than two tiles each) by TX = 64 - 2R columns; lane l of each wave
 // holds column x0 - R + l, so a wave row covers the tile plus an R-wide halo on
 // both sides.  u^k is staged in LDS with a 2R halo.  Every thread owns NQ
 // consecutive rows of one column and keeps that column in registers (z
@@ -120,11 +121,11 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uin
 // mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8 gives every XCD a
 // contiguous run of tiles whose halos then hit in that XCD's L2.
 // ---------------------------------------------------------------------------
-template <int R, int NSTEP, bool FAST>
+template <int R, int NSTEP, bool FAST, int TZ>
 __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot, int tile,
                                             int x0, int z0, float (*U)[64 + 2 * R], float (*V)[64]) {
 #pragma clang fp contract(off)
-    constexpr int TX = t2x(R), TZ = T2Z;
+    constexpr int TX = t2x(R);
     constexpr int SH = TZ + 4 * R;            // staged rows of u^k
     constexpr int NQ = TZ / 4;                // rows per thread
     constexpr int NS = (SH + 3) / 4;          // staged rows per thread
@@ -302,9 +303,9 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
     }
 }
 
-template <int R, int NSTEP>
+template <int R, int NSTEP, int TZ>
 __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph, const StepArgs a) {
-    constexpr int TX = t2x(R), TZ = T2Z;
+    constexpr int TX = t2x(R);
     __shared__ float U[TZ + 4 * R][64 + 2 * R];
     __shared__ float V[NSTEP == 2 ? TZ + 2 * R : 1][64];
     const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2], nsp = ntx * ntz;
@@ -322,8 +323,8 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
                       z0 + TZ + 2 * R <= (int)L.P[2] && x0 - R >= nb && z0 - R >= nb &&
                       x0 + TX + R <= nb + (int)L.n[0] && z0 + TZ + R <= nb + (int)L.n[2];
     const int tile = (shot * ntz + bz) * ntx + bx;
-    if (fast) step2d_body<R, NSTEP, true>(L, ph, a, shot, tile, x0, z0, U, V);
-    else step2d_body<R, NSTEP, false>(L, ph, a, shot, tile, x0, z0, U, V);
+    if (fast) step2d_body<R, NSTEP, true, TZ>(L, ph, a, shot, tile, x0, z0, U, V);
+    else step2d_body<R, NSTEP, false, TZ>(L, ph, a, shot, tile, x0, z0, U, V);
 
     const int per_shot = ntx * ntz;
     if (a.do_sample) sample_points<4>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bz * ntx + bx, per_shot);
@@ -525,13 +526,17 @@ hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hi
     if (L.ndim == 2) {
         const int64_t nlog = L.ntiles[0] * L.ntiles[2] * L.S;
         dim3 grid((unsigned)((nlog + 7) / 8 * 8));
+        if (L.tile[2] != T2Z && L.tile[2] != T2Z_SMALL) return hipErrorInvalidValue;
+        const bool small = L.tile[2] == T2Z_SMALL;
+#define TPX_STEP2D(RR, NS, TZ) hipLaunchKernelGGL((k_step2d<RR, NS, TZ>), grid, dim3(256), 0, stream, L, ph, a)
         if (a.nstep == 2) {
-            if (L.R == 2) hipLaunchKernelGGL((k_step2d<2, 2>), grid, dim3(256), 0, stream, L, ph, a);
-            else hipLaunchKernelGGL((k_step2d<4, 2>), grid, dim3(256), 0, stream, L, ph, a);
+            if (L.R == 2) { if (small) TPX_STEP2D(2, 2, T2Z_SMALL); else TPX_STEP2D(2, 2, T2Z); }
+            else { if (small) TPX_STEP2D(4, 2, T2Z_SMALL); else TPX_STEP2D(4, 2, T2Z); }
         } else {
-            if (L.R == 2) hipLaunchKernelGGL((k_step2d<2, 1>), grid, dim3(256), 0, stream, L, ph, a);
-            else hipLaunchKernelGGL((k_step2d<4, 1>), grid, dim3(256), 0, stream, L, ph, a);
+            if (L.R == 2) { if (small) TPX_STEP2D(2, 1, T2Z_SMALL); else TPX_STEP2D(2, 1, T2Z); }
+            else { if (small) TPX_STEP2D(4, 1, T2Z_SMALL); else TPX_STEP2D(4, 1, T2Z); }
         }
+#undef TPX_STEP2D
     } else {
         if (a.nstep != 1) return hipErrorInvalidValue;
         const int64_t zchunks = (L.P[2] + T3Z - 1) / T3Z;

@@ -182,8 +182,12 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
     // the step kernels address one shot's field with 32-bit byte offsets
     if (L.shot_floats >= (int64_t)1 << 30) return fail(TPX_E_INVAL, "one shot's field exceeds 2^30 floats");
     if (L.ndim == 2) {
-        L.tile[0] = t2x(L.R); L.tile[1] = 1; L.tile[2] = T2Z;
-        L.map[0] = 64; L.map[1] = 1; L.map[2] = T2Z + 2 * L.R;
+        // tile height: the default unless a launch would give the 256 CUs
+        // fewer than two tiles each
+        const int64_t tiles32 = L.S * ((L.P[0] + t2x(L.R) - 1) / t2x(L.R)) * ((L.P[2] + T2Z - 1) / T2Z);
+        const int tz = tiles32 < 512 ? T2Z_SMALL : T2Z;
+        L.tile[0] = t2x(L.R); L.tile[1] = 1; L.tile[2] = tz;
+        L.map[0] = 64; L.map[1] = 1; L.map[2] = tz + 2 * L.R;
         L.map_org[0] = -L.R; L.map_org[1] = 0; L.map_org[2] = -L.R;
     } else {
         L.tile[0] = T3X; L.tile[1] = T3Y; L.tile[2] = 1;
