@@ -21,12 +21,39 @@ from __future__ import annotations
 import collections
 import time
 from dataclasses import dataclass
-from typing import Dict, List, Optional
+from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
 
 from . import tpx
+
+
+def admission_plan(waiting: Sequence, slots: int, free_bytes: float, budget: float, nlarge: int, max_large: int,
+                   need: Callable, large: Callable):
+    """The waiting requests to admit now and those to reject, scanned in arrival
+    order: a request needing more than the whole budget is rejected; a large one
+    is passed over while `max_large` large jobs run (smaller ones behind it may
+    go first); the first request that does not fit the free bytes ends the
+    scan, so memory is granted in arrival order.  At most `slots` are admitted.
+    need(req) gives a request's device bytes, large(req) whether it is large."""
+    admit, reject = [], []
+    for req in waiting:
+        if len(admit) >= slots:
+            break
+        n = need(req)
+        if n > budget:
+            reject.append(req)
+            continue
+        lg = bool(large(req))
+        if lg and nlarge >= max_large:
+            continue
+        if n > free_bytes:
+            break
+        admit.append(req)
+        free_bytes -= n
+        nlarge += lg
+    return admit, reject
 
 
 @dataclass
@@ -126,34 +153,30 @@ class Server:
                 if not st.cancelled and st.req.cancel_at is not None and st.req.cancel_at <= now:
                     st.cancelled = True
                     results[st.req.rid].status = "cancelled"
-            # admission at chunk boundaries, in arrival order; a large request
-            # blocked by a running large job lets smaller ones pass
-            nlarge = sum(1 for st in active if self._large(st.req))
-            for req in list(waiting):
-                if len(active) >= self.max_active or not free_streams:
-                    break
+            # admission at chunk boundaries
+            def need(req):
                 if req.rid not in wsb:
                     wsb[req.rid] = req.workspace_bytes()
-                need = wsb[req.rid] + 4 * int(np.prod(req.grid.shape)) + 8
-                if need > self.budget:
-                    waiting.remove(req)
-                    results[req.rid].status = "rejected: workspace exceeds the HBM budget"
-                    results[req.rid].finished = now
-                    continue
-                large = self._large(req)
-                if large and nlarge >= self.max_large:
-                    continue
-                if used + need > self.budget:
-                    break
+                return wsb[req.rid] + 4 * int(np.prod(req.grid.shape)) + 8
+
+            nlarge = sum(1 for st in active if self._large(st.req))
+            slots = min(self.max_active - len(active), len(free_streams))
+            admit, reject = admission_plan(list(waiting), slots, self.budget - used, self.budget, nlarge,
+                                           self.max_large, need, self._large)
+            for req in reject:
                 waiting.remove(req)
-                nlarge += 1 if large else 0
+                results[req.rid].status = "rejected: workspace exceeds the HBM budget"
+                results[req.rid].finished = now
+            for req in admit:
+                waiting.remove(req)
+                nlarge += 1 if self._large(req) else 0
                 stream = free_streams.pop()
                 with torch.cuda.stream(stream):
                     ws = torch.empty(wsb[req.rid], dtype=torch.uint8, device=self.device)
                     job = tpx.Job(req.grid, req.geom, req.probe, req.m, req.d_obs, ws=ws, stream=stream)
-                active.append(_Active(req, job, stream, need, now))
+                active.append(_Active(req, job, stream, need(req), now))
                 results[req.rid].admitted = now
-                used += need
+                used += need(req)
                 self.peak_active = max(self.peak_active, len(active))
                 self.peak_large = max(self.peak_large, nlarge)
                 self.peak_bytes = max(self.peak_bytes, used)
