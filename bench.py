@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--probe", default=None, help="rademacher | gauss_b64 | range_finder")
     ap.add_argument("--block", type=int, default=0, help="time steps per probe contraction (0 = default)")
     ap.add_argument("--keep-vbar", action="store_true", help="accumulate vbar instead of folding it")
+    ap.add_argument("--full", action="store_true",
+                    help="time the full-storage exact gradient (Eq. 3) instead of the probed one")
     ap.add_argument("--dtt-side", type=int, default=0, choices=[0, 1],
                     help="1: probe the second time difference of u and lambda itself (Algorithm 1 as printed)")
     ap.add_argument("--imaging", type=int, default=0, choices=[0, 1],
@@ -124,13 +126,19 @@ def main():
                       dtt_side=args.dtt_side, imaging=args.imaging)
 
     d_obs = tpx.forward(grid, geom, m_true)           # synthetic observed data (untimed input)
-    ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_PROBED, grid, geom, probe, dev)
+    ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_FULL if args.full else tpx.CALL_GRADIENT_PROBED, grid, geom,
+                             None if args.full else probe, dev)
     g = torch.empty(tuple(wl.shape), dtype=torch.float32, device=dev)
     J = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
     def step():
-        tpx.gradient_probed(grid, geom, probe, m_0, d_obs, ws=ws, g_out=g, J_out=J, stream=stream)
+        if args.full:   # the exact gradient from the stored history (Eq. 3), for comparison
+            g_f, J_f = tpx.gradient_full(grid, geom, m_0, d_obs, ws=ws, stream=stream)
+            g.copy_(g_f)
+            J.copy_(J_f)
+        else:
+            tpx.gradient_probed(grid, geom, probe, m_0, d_obs, ws=ws, g_out=g, J_out=J, stream=stream)
 
     for _ in range(args.warmup):
         step()
@@ -178,7 +186,8 @@ def main():
         step()
         torch.cuda.synchronize()
         for name, kid in (("step2", tpx.KERNEL_STEP2), ("step", tpx.KERNEL_STEP),
-                          ("accum_fwd", tpx.KERNEL_ACCUM_FWD), ("accum_adj", tpx.KERNEL_ACCUM_ADJ)):
+                          ("accum_fwd", tpx.KERNEL_ACCUM_FWD), ("accum_adj", tpx.KERNEL_ACCUM_ADJ),
+                          ("accum_full", tpx.KERNEL_ACCUM_FULL)):
             tot, n = tpx.profile_read(kid)
             if n or name != "step2":
                 kernels[name] = {"total_ms": round(tot, 4), "launches": n,
@@ -207,7 +216,7 @@ def main():
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------------------
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.full:
         # about 10-30 s of oracle work: the full record of one 2D shot, or a
         # short window of the 3D record
         cpu = cpu_baseline(wl, r, kind, args.cpu_nt or (wl.nt if wl.ndim == 2 else 24),
@@ -234,6 +243,8 @@ def main():
                    "overlap_contractions": bool(tpx.get_option(tpx.OPT_OVERLAP_CONTRACTIONS)),
                    "matrix_core_contractions": matrix_core_use(kind, r, bool(args.keep_vbar)),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
+        "gradient": "full-storage (Eq. 3)" if args.full else "probed (Eq. 4)",
+        "workspace_GB": round(ws.numel() / 1e9, 3),
         "host_enqueue_ms": round(host_enqueue_ms, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},
