@@ -100,8 +100,8 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uin
 // ---------------------------------------------------------------------------
 // 2D leapfrog steps, one or two per launch.
 //
-// A block owns a tile of TZ rows (T2Z, or T2Z_SMALL when a launch would give
-// the CUs fewer than two tiles each) by TX = 64 - 2R columns; lane l of each wave
+// A block owns a tile of TZ rows (T2Z; T2Z_MID or T2Z_SMALL when a launch would
+// give the CUs fewer than two tiles each) by TX = 64 - 2R columns; lane l of each wave
 // holds column x0 - R + l, so a wave row covers the tile plus an R-wide halo on
 // both sides.  u^k is staged in LDS with a 2R halo.  Every thread owns NQ
 // consecutive rows of one column and keeps that column in registers (z
@@ -526,15 +526,21 @@ hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hi
     if (L.ndim == 2) {
         const int64_t nlog = L.ntiles[0] * L.ntiles[2] * L.S;
         dim3 grid((unsigned)((nlog + 7) / 8 * 8));
-        if (L.tile[2] != T2Z && L.tile[2] != T2Z_SMALL) return hipErrorInvalidValue;
-        const bool small = L.tile[2] == T2Z_SMALL;
-#define TPX_STEP2D(RR, NS, TZ) hipLaunchKernelGGL((k_step2d<RR, NS, TZ>), grid, dim3(256), 0, stream, L, ph, a)
+        const int tz = (int)L.tile[2];
+        if (tz != T2Z && tz != T2Z_MID && tz != T2Z_SMALL) return hipErrorInvalidValue;
+#define TPX_STEP2D(RR, NS)                                                                          \
+    do {                                                                                            \
+        if (tz == T2Z) hipLaunchKernelGGL((k_step2d<RR, NS, T2Z>), grid, dim3(256), 0, stream, L, ph, a); \
+        else if (tz == T2Z_MID)                                                                     \
+            hipLaunchKernelGGL((k_step2d<RR, NS, T2Z_MID>), grid, dim3(256), 0, stream, L, ph, a);  \
+        else hipLaunchKernelGGL((k_step2d<RR, NS, T2Z_SMALL>), grid, dim3(256), 0, stream, L, ph, a); \
+    } while (0)
         if (a.nstep == 2) {
-            if (L.R == 2) { if (small) TPX_STEP2D(2, 2, T2Z_SMALL); else TPX_STEP2D(2, 2, T2Z); }
-            else { if (small) TPX_STEP2D(4, 2, T2Z_SMALL); else TPX_STEP2D(4, 2, T2Z); }
+            if (L.R == 2) TPX_STEP2D(2, 2);
+            else TPX_STEP2D(4, 2);
         } else {
-            if (L.R == 2) { if (small) TPX_STEP2D(2, 1, T2Z_SMALL); else TPX_STEP2D(2, 1, T2Z); }
-            else { if (small) TPX_STEP2D(4, 1, T2Z_SMALL); else TPX_STEP2D(4, 1, T2Z); }
+            if (L.R == 2) TPX_STEP2D(2, 1);
+            else TPX_STEP2D(4, 1);
         }
 #undef TPX_STEP2D
     } else {

@@ -185,7 +185,7 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
         // tile height: the default unless a launch would give the 256 CUs
         // fewer than two tiles each
         const int64_t tiles32 = L.S * ((L.P[0] + t2x(L.R) - 1) / t2x(L.R)) * ((L.P[2] + T2Z - 1) / T2Z);
-        const int tz = tiles32 < 512 ? T2Z_SMALL : T2Z;
+        const int tz = tiles32 >= 512 ? T2Z : (tiles32 >= 384 ? T2Z_MID : T2Z_SMALL);
         L.tile[0] = t2x(L.R); L.tile[1] = 1; L.tile[2] = tz;
         L.map[0] = 64; L.map[1] = 1; L.map[2] = tz + 2 * L.R;
         L.map_org[0] = -L.R; L.map_org[1] = 0; L.map_org[2] = -L.R;

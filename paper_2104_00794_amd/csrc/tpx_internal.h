@@ -27,10 +27,12 @@ constexpr int XO = 32;
 // 2D step kernel tile: T2Z rows by 64 - 2R columns of outputs, 256 threads.
 // One wave spans the tile's columns plus an R-wide halo on each side: the
 // region on which the first of two fused steps is computed.  Problems too
-// small to give every CU two such tiles per launch use tiles of T2Z_SMALL
-// rows instead (twice the tiles, more halo work per tile).
+// small to give every CU two such tiles per launch use shorter tiles (more
+// tiles, more halo work per tile): T2Z_MID rows down to 384 tiles of T2Z
+// rows, T2Z_SMALL rows below that.
 constexpr int T2Z = 32;
-constexpr int T2Z_SMALL = 16;
+constexpr int T2Z_MID = 16;
+constexpr int T2Z_SMALL = 8;
 __host__ __device__ constexpr int t2x(int R) { return 64 - 2 * R; }
 // 3D step kernel tile: 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
