@@ -185,3 +185,17 @@ def test_largest_shot_field_accepted_and_the_next_rejected():
     assert tpx.workspace_bytes(tpx.CALL_FORWARD, tpx.Grid((900, 900, 900), **g3), geom3) >= 3 * 992 * 948 * 948 * 4
     with pytest.raises(tpx.TpxError):
         tpx.workspace_bytes(tpx.CALL_FORWARD, tpx.Grid((1000, 1000, 1000), **g3), geom3)
+
+
+def test_binding_checks_tensors_before_any_call():
+    # host tensors, wrong dtypes and wrong shapes are refused by the binding
+    import torch
+    grid = tpx.Grid(**GRID)
+    geom = _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]]])
+    m_cpu = torch.ones(30, 40)
+    with pytest.raises(TypeError):
+        tpx.forward(grid, geom, m_cpu)
+    with pytest.raises(TypeError):
+        tpx.gradient_probed(grid, geom, tpx.Probe(r=4), m_cpu, torch.zeros(1, 100, 1))
+    with pytest.raises(TypeError):
+        tpx.gradient_full(grid, geom, torch.ones(30, 40, dtype=torch.float64), torch.zeros(1, 100, 1))
