@@ -68,7 +68,26 @@ def parse():
     ap.add_argument("--large-points", type=float, default=3e6,
                     help="padded points over a job's shots from which it counts as large")
     ap.add_argument("--max-large", type=int, default=2, help="large jobs the server runs at once")
+    ap.add_argument("--c3-steps", type=int, default=3,
+                    help="timed gradient calls of the 3D workload for the c3 sub-record (0: skip)")
+    ap.add_argument("--serving-requests", type=int, default=60,
+                    help="requests of the serving sub-record (0: skip)")
+    ap.add_argument("--fused-3d", type=int, default=None, choices=[0, 1],
+                    help="two leapfrog steps per 3D launch (library option; default: the library's)")
     return ap.parse_args()
+
+
+def stencil_bytes(S: int) -> float:
+    """Algorithmic HBM bytes of one leapfrog step per shot and padded point: read
+    u^k and u^{k-1}, write u^{k+1}, and beta read once for the S batched shots."""
+    return 12.0 + 4.0 / S
+
+
+def path_bytes(S: int, phi: float) -> float:
+    """Algorithmic bytes per shot-point-step of the whole probed path: the
+    stencil, plus one re-read of each probed sample by the time-blocked
+    contraction (phi = physical / padded points)."""
+    return stencil_bytes(S) + 4.0 * phi
 
 
 def main():
@@ -105,14 +124,104 @@ def main():
     tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 1 if args.overlap else 0)
     if args.matrix_cores is not None:
         tpx.set_option(tpx.OPT_MATRIX_CORES, args.matrix_cores)
+    if args.fused_3d is not None:
+        tpx.set_option(tpx.OPT_FUSED_STEPS_3D, args.fused_3d)
     if args.serving:
-        return serving(args, dev)
+        print(json.dumps(serving(args, dev)), flush=True)
+        return
 
     wl = workload(args.workload)
     if args.nt:
         wl = wl.with_(nt=args.nt)
-    r = args.r or wl.r
-    kind = args.probe or wl.probe
+    rec = gradient_record(args, wl, args.steps, args.warmup, dev, profile=not args.no_profile_pass)
+    progress("headline workload %s done: %.1f GPts/s" % (wl.name, rec["value"]))
+
+    # ---- reference rate: a plain device copy of 1 GiB (after the timed region) ------------
+    copy_gbps = None if args.no_profile_pass else copy_bandwidth(dev)
+
+    # ---- the 3D workload whose full-storage gradient cannot fit on the GPU ------------------
+    c3 = None
+    if args.c3_steps > 0 and args.workload != "c3_layered_3d" and not args.full:
+        wl3 = workload("c3_layered_3d")
+        torch.cuda.empty_cache()
+        r3 = gradient_record(args, wl3, args.c3_steps, 1, dev, profile=not args.no_profile_pass, default_probe=True)
+        c3 = {k: r3[k] for k in ("value", "unit", "value_physical_points", "ms_per_step", "steps", "latency_ms",
+                                  "hbm_roofline_pct", "b_alg_bytes_per_point_step", "roofline", "memory",
+                                  "workspace_GB", "kernels", "config", "J")}
+        torch.cuda.empty_cache()
+        progress("c3 done: %.1f GPts/s" % c3["value"])
+
+    # ---- serving mix: continuous batching against the plain path ---------------------------
+    srv = None
+    if args.serving_requests > 0 and not args.full:
+        sargs = argparse.Namespace(**vars(args))
+        sargs.requests = args.serving_requests
+        sargs.saturation = False
+        srv = serving(sargs, dev)
+        progress("serving done")
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------------------
+    cpu = None
+    if not args.no_cpu_baseline and not args.full:
+        # about 10-30 s of oracle work in all: the full record of a few 2D
+        # shots, or a short window of the 3D record, timed three times
+        cpu = cpu_baseline(wl, rec["config"]["r"], rec["config"]["probe"],
+                           args.cpu_nt or (wl.nt if wl.ndim == 2 else 8),
+                           min(2, wl.nshots) if wl.ndim == 2 else 1, reps=3)
+
+    out = {
+        "metric": "GPts/s fwd+adj with r-probe accumulation (%HBM roofline); gradient p50/p99 latency",
+        "value": rec["value"],
+        "unit": "GPts/s",
+        "value_physical_points": rec["value_physical_points"],
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rec["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": rec["config"],
+        "gradient": rec["gradient"],
+        "workspace_GB": rec["workspace_GB"],
+        "memory": rec["memory"],
+        "host_enqueue_ms": rec["host_enqueue_ms"],
+        "latency_ms": rec["latency_ms"],
+        "hbm_roofline_pct": rec["hbm_roofline_pct"],
+        "b_alg_bytes_per_point_step": rec["b_alg_bytes_per_point_step"],
+        "hbm_roofline_pct_stencil_only": rec["hbm_roofline_pct_stencil_only"],
+        "roofline": rec["roofline"],
+        "roofline_fused_launch": rec["roofline_fused_launch"],
+        "copy_GBps": copy_gbps,
+        "kernels": rec["kernels"],
+        "kernel_timing": "HIP events on the launch stream around each run of consecutive launches of one "
+                         "kernel kind, in one profiled call after the timed region",
+        "c3": c3,
+        "serving": srv,
+        "cpu_baseline": cpu,
+        "J": rec["J"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def progress(msg: str) -> None:
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def gradient_record(args, wl, steps, warmup, dev, profile=True, default_probe=False):
+    """Time `steps` complete gradient calls of workload `wl` (inputs resident in
+    HBM), then one profiled call for the per-kernel durations."""
+    import torch
+    from paper_2104_00794_amd import tpx
+    r = wl.r if default_probe else (args.r or wl.r)
+    kind = wl.probe if default_probe else (args.probe or wl.probe)
+    keep_vbar = False if default_probe else bool(args.keep_vbar or args.imaging)
+    dtt_side = 0 if default_probe else args.dtt_side
+    imaging = 0 if default_probe else args.imaging
+    block = 0 if default_probe else args.block
+    full = False if default_probe else args.full
     mt, m0 = wl.models()
     grid = tpx.Grid(wl.shape, h=wl.h, dt=wl.dt, nt=wl.nt, order=wl.order, nbl=wl.nbl, damp_vmax=wl.vmax,
                     damp_R=wl.damp_R)
@@ -120,42 +229,42 @@ def main():
     geom = tpx.Geometry(wl.src_pos(), wl.rec_pos(), wav)
     m_true = torch.tensor(mt, dtype=torch.float32, device=dev)
     m_0 = torch.tensor(m0, dtype=torch.float32, device=dev)
-    if args.imaging:
-        args.keep_vbar = True
-    probe = tpx.Probe(kind=kind, r=r, seed=wl.probe_seed, block=args.block, keep_vbar=args.keep_vbar,
-                      dtt_side=args.dtt_side, imaging=args.imaging)
+    del mt, m0
+    probe = tpx.Probe(kind=kind, r=r, seed=wl.probe_seed, block=block, keep_vbar=keep_vbar,
+                      dtt_side=dtt_side, imaging=imaging)
 
     d_obs = tpx.forward(grid, geom, m_true)           # synthetic observed data (untimed input)
-    ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_FULL if args.full else tpx.CALL_GRADIENT_PROBED, grid, geom,
-                             None if args.full else probe, dev)
+    del m_true
+    ws = tpx.alloc_workspace(tpx.CALL_GRADIENT_FULL if full else tpx.CALL_GRADIENT_PROBED, grid, geom,
+                             None if full else probe, dev)
     g = torch.empty(tuple(wl.shape), dtype=torch.float32, device=dev)
     J = torch.empty(1, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
     def step():
-        if args.full:   # the exact gradient from the stored history (Eq. 3), for comparison
+        if full:   # the exact gradient from the stored history (Eq. 3), for comparison
             g_f, J_f = tpx.gradient_full(grid, geom, m_0, d_obs, ws=ws, stream=stream)
             g.copy_(g_f)
             J.copy_(J_f)
         else:
             tpx.gradient_probed(grid, geom, probe, m_0, d_obs, ws=ws, g_out=g, J_out=J, stream=stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     tpx.check_workspace(ws)
 
-    # ---- timed region: K complete gradient calls ------------------------------------------
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # ---- timed region: `steps` complete gradient calls ------------------------------------
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         ev[i][0].record(stream)
         step()
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    ms_per_step = (t1 - t0) * 1e3 / steps
     lat = np.array([a.elapsed_time(b) for a, b in ev])
     # host time to enqueue one call (the call returns once its work is queued)
     torch.cuda.synchronize()
@@ -168,20 +277,12 @@ def main():
     updates = S * npad * 2 * (nt - 1)
     gpts = updates / (ms_per_step * 1e-3) / 1e9
     phi = nphys / npad
-    # algorithmic HBM bytes per shot-point-step of the whole path: the 2D path
-    # fuses two leapfrog steps per pass (reads u^{k-1}, u^k, beta once, writes
-    # two levels); 3D takes one step per pass; every level is read once more by
-    # the probe contraction
-    b_alg_step = (16.0 + 4.0 / S) / 2.0 if wl.ndim == 2 else 12.0 + 4.0 / S
-    b_alg_path = b_alg_step + 4.0 * phi
-    # the same path priced one step per pass (12 + 4/S + 4 phi): what an unfused
-    # leapfrog must move, and a looser bound than the fused model above
-    b_alg_one_step = 12.0 + 4.0 / S + 4.0 * phi
+    b_alg = path_bytes(S, phi)
 
     # ---- per-kernel durations (HIP events on the launch stream) ----------------------------
     kernels = {}
-    roofline = None
-    if not args.no_profile_pass:
+    roofline = fused = None
+    if profile:
         tpx.profile_enable(True)
         step()
         torch.cuda.synchronize()
@@ -189,84 +290,74 @@ def main():
                           ("accum_fwd", tpx.KERNEL_ACCUM_FWD), ("accum_adj", tpx.KERNEL_ACCUM_ADJ),
                           ("accum_full", tpx.KERNEL_ACCUM_FULL)):
             tot, n = tpx.profile_read(kid)
-            if n or name != "step2":
-                kernels[name] = {"total_ms": round(tot, 4), "launches": n,
-                                 "avg_us": round(1e3 * tot / n, 3) if n else None}
+            kernels[name] = {"total_ms": round(tot, 4), "launches": n,
+                             "avg_us": round(1e3 * tot / n, 3) if n else None}
         tpx.profile_enable(False)
         # dominant kernel: the step kernel with the larger total time
-        two = "step2" in kernels and kernels["step2"]["total_ms"] >= kernels["step"]["total_ms"]
+        two = kernels["step2"]["total_ms"] >= kernels["step"]["total_ms"]
         st = kernels["step2" if two else "step"]
+        nstep = 2 if two else 1
+        R = wl.order // 2
+        if wl.ndim == 2:
+            kname, tag = "k_step2d<R=%d,NSTEP=%d>" % (R, nstep), "k_step2d_x2" if two else "k_step2d"
+        else:
+            kname, tag = ("k_step3d2<R=%d>" % R, "k_step3d2") if two else ("k_step3d<R=%d>" % R, "k_step3d")
         if st["launches"]:
-            # one launch reads u^{k-1}, u^k (all shots) and beta once, writes 1 or 2 levels
-            bytes_per_launch = S * npad * (16.0 if two else 12.0) + npad * 4.0
+            # the paper's leapfrog traffic per shot-point-step, times the steps one launch advances
+            bytes_per_launch = nstep * S * npad * stencil_bytes(S)
             achieved = bytes_per_launch / (st["avg_us"] * 1e-6) / 1e9
-            R = wl.order // 2
-            tag = ("k_step2d_x2" if two else "k_step2d") if wl.ndim == 2 else "k_step3d"
             traffic = profiling.read_traffic(wl.name, tag)   # None unless measured with this kernel source
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                        "kernel": ("k_step2d<R=%d,NSTEP=%d>" % (R, 2 if two else 1)) if wl.ndim == 2 else
-                        "k_step3d<R=%d>" % R,
-                        "bytes_per_launch": bytes_per_launch, "avg_launch_us": st["avg_us"]}
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kname,
+                        "steps_per_launch": nstep, "bytes_per_launch": bytes_per_launch,
+                        "bytes_per_shot_point_step": round(stencil_bytes(S), 4), "avg_launch_us": st["avg_us"]}
+            # what a launch of nstep fused steps must move at least: u^{k-1}, u^k and beta once,
+            # nstep new levels written
+            fb = S * npad * (8.0 + 4.0 * nstep) + npad * 4.0
+            fa = fb / (st["avg_us"] * 1e-6) / 1e9
+            fused = {"bytes_per_launch": fb, "achieved": round(fa, 1), "frac": round(fa / HBM_PEAK_GBS, 4)}
 
-    # ---- reference rate: a plain device copy of 1 GiB (after the timed region) ------------
-    copy_gbps = None
-    if not args.no_profile_pass:
-        copy_gbps = copy_bandwidth(dev)
+    # ---- memory: probed workspace against the stored forward history -----------------------
+    hist = S * nphys * nt * 4.0                       # the history of Eq. 3 (N x n_t values per shot)
+    full_ws = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom, None)
+    memory = {"workspace_GB": round(ws.numel() / 1e9, 3),
+              "history_GB": round(hist / 1e9, 3),
+              "full_storage_workspace_GB": round(full_ws / 1e9, 3),
+              "accumulators_GB": round(S * r * nphys * 4.0 / 1e9, 3),
+              "reduction_vs_history": round(hist / ws.numel(), 2),
+              "paper_reduction_nt_over_2r": round(nt / (2.0 * r), 2)}
 
-    # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------------------
-    cpu = None
-    if not args.no_cpu_baseline and not args.full:
-        # about 10-30 s of oracle work: the full record of one 2D shot, or a
-        # short window of the 3D record
-        cpu = cpu_baseline(wl, r, kind, args.cpu_nt or (wl.nt if wl.ndim == 2 else 24),
-                           min(4, wl.nshots) if wl.ndim == 2 else 1)
-
-    out = {
-        "metric": "GPts/s fwd+adj with r-probe accumulation (%HBM roofline); gradient p50/p99 latency",
-        "value": round(gpts, 3),
-        "unit": "GPts/s",
-        "value_physical_points": round(gpts * phi, 3),   # the same rate counting physical nodes only
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
+    return {
+        "value": round(gpts, 3), "unit": "GPts/s", "value_physical_points": round(gpts * phi, 3),
+        "steps": steps, "ms_per_step": round(ms_per_step, 3),
         "config": {"workload": wl.name, "grid": "x".join(str(s) for s in wl.shape[::-1]), "h_m": wl.h,
                    "space_order": wl.order, "shots": S, "nt": nt, "nbl": wl.nbl, "r": r, "probe": kind,
-                   "block": args.block or "default", "keep_vbar": bool(args.keep_vbar),
-                   "dtt_side": args.dtt_side, "imaging": args.imaging,
+                   "block": block or "default", "keep_vbar": keep_vbar, "dtt_side": dtt_side, "imaging": imaging,
                    "overlap_contractions": bool(tpx.get_option(tpx.OPT_OVERLAP_CONTRACTIONS)),
-                   "matrix_core_contractions": matrix_core_use(kind, r, bool(args.keep_vbar)),
+                   "fused_steps_3d": bool(tpx.get_option(tpx.OPT_FUSED_STEPS_3D)),
+                   "matrix_core_contractions": matrix_core_use(kind, r, keep_vbar),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
-        "gradient": "full-storage (Eq. 3)" if args.full else "probed (Eq. 4)",
+        "gradient": "full-storage (Eq. 3)" if full else "probed (Eq. 4)",
         "workspace_GB": round(ws.numel() / 1e9, 3),
+        "memory": memory,
         "host_enqueue_ms": round(host_enqueue_ms, 2),
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                        "p99": round(float(np.percentile(lat, 99)), 3)},
-        "hbm_roofline_pct": round(100.0 * gpts * b_alg_path / HBM_PEAK_GBS, 2),
-        "b_alg_bytes_per_point_step": round(b_alg_path, 3),
-        "hbm_roofline_pct_one_step_model": round(100.0 * gpts * b_alg_one_step / HBM_PEAK_GBS, 2),
-        # the stencil's bytes alone (12 + 4/S, one step per pass), without the probe re-read
-        "hbm_roofline_pct_stencil_only": round(100.0 * gpts * (12.0 + 4.0 / S) / HBM_PEAK_GBS, 2),
+        "hbm_roofline_pct": round(100.0 * gpts * b_alg / HBM_PEAK_GBS, 2),
+        "b_alg_bytes_per_point_step": round(b_alg, 3),
+        # the stencil's bytes alone (12 + 4/S), without the probe re-read
+        "hbm_roofline_pct_stencil_only": round(100.0 * gpts * stencil_bytes(S) / HBM_PEAK_GBS, 2),
         "roofline": roofline,
-        "copy_GBps": copy_gbps,
+        "roofline_fused_launch": fused,
         "kernels": kernels,
-        "kernel_timing": "HIP events on the launch stream around each run of consecutive launches of one "
-                         "kernel kind, in one profiled call after the timed region",
-        "cpu_baseline": cpu,
         "J": float(J.item()),
     }
-    print(json.dumps(out), flush=True)
 
 
 def serving(args, dev):
     """Serving mix: p50/p99 latency and aggregate GPts/s, continuous batching vs
-    the plain one-at-a-time path on the same Poisson arrival trace."""
+    the plain one-at-a-time path on the same Poisson arrival trace (and, with
+    `args.saturation`, with every request queued at once)."""
     import torch
     from paper_2104_00794_amd import serve, tpx
     from paper_2104_00794_amd.inputs import serving_workload
@@ -297,18 +388,22 @@ def serving(args, dev):
     bat = srv.run(reqs)
     same = all(torch.equal(seq[q.rid].g, bat[q.rid].g) for q in reqs if bat[q.rid].status == "ok")
     a, b = serve.summarize(seq, reqs), serve.summarize(bat, reqs)
-    # saturation: every request queued at once, so the makespan measures how
-    # much work the GPU absorbs when jobs overlap (small grids alone leave most
-    # of the 256 CUs idle)
-    for q in reqs:
-        q.arrival = 0.0
     print("serving: server on the Poisson trace done", file=sys.stderr, flush=True)
-    sat_seq = serve.summarize(serve.run_sequential(reqs), reqs)
-    print("serving: plain path at saturation done", file=sys.stderr, flush=True)
-    srv2 = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=args.chunk_steps,
-                        max_active=args.max_active, nstreams=8, inflight=args.inflight,
-                        large_points=args.large_points, max_large=args.max_large)
-    sat_bat = serve.summarize(srv2.run(reqs), reqs)
+    saturated = None
+    if getattr(args, "saturation", True):
+        # saturation: every request queued at once, so the makespan measures how
+        # much work the GPU absorbs when jobs overlap (small grids alone leave most
+        # of the 256 CUs idle)
+        for q in reqs:
+            q.arrival = 0.0
+        sat_seq = serve.summarize(serve.run_sequential(reqs), reqs)
+        print("serving: plain path at saturation done", file=sys.stderr, flush=True)
+        srv2 = serve.Server(hbm_budget_bytes=args.budget_gb * 1e9, chunk_steps=args.chunk_steps,
+                            max_active=args.max_active, nstreams=8, inflight=args.inflight,
+                            large_points=args.large_points, max_large=args.max_large)
+        sat_bat = serve.summarize(srv2.run(reqs), reqs)
+        saturated = {"batched": sat_bat, "sequential": sat_seq,
+                     "throughput_ratio": round(sat_bat["gpts_per_s"] / sat_seq["gpts_per_s"], 3)}
     out = {
         "metric": "serving: gradient p50/p99 latency and aggregate GPts/s, continuous batching vs one-at-a-time",
         "value": b["gpts_per_s"], "unit": "GPts/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
@@ -320,16 +415,19 @@ def serving(args, dev):
                    "max_active": args.max_active, "inflight": args.inflight,
                    "large_points": args.large_points, "max_large": args.max_large},
         "batched": b, "sequential": a, "mean_service_ms": round(1e3 * mean_service, 2),
-        "saturated": {"batched": sat_bat, "sequential": sat_seq,
-                      "throughput_ratio": round(sat_bat["gpts_per_s"] / sat_seq["gpts_per_s"], 3)},
+        "p99_ratio_sequential_over_batched": round(a["p99_ms"] / b["p99_ms"], 3),
+        "p50_ratio_sequential_over_batched": round(a["p50_ms"] / b["p50_ms"], 3),
+        "saturated": saturated,
         "peak_active_jobs": srv.peak_active, "peak_workspace_gb": round(srv.peak_bytes / 1e9, 2),
         "results_identical": bool(same),
     }
-    print(json.dumps(out), flush=True)
+    del reqs, seq, bat
+    return out
 
 
-def cpu_baseline(wl, r, kind, nt_sample, shots):
-    """FP64 oracle on the first `shots` shots of the workload, first nt_sample time steps."""
+def cpu_baseline(wl, r, kind, nt_sample, shots, reps=3):
+    """FP64 oracle on the first `shots` shots of the workload, first nt_sample
+    time steps; the median of `reps` timed runs."""
     import oracle
     oracle.build(force=False)
     sample = wl.with_(nt=nt_sample, src=wl.src[:shots])
@@ -338,21 +436,36 @@ def cpu_baseline(wl, r, kind, nt_sample, shots):
                      damp_vmax=sample.vmax, damp_R=sample.damp_R)
     # the sample's observed traces, modelled by the oracle itself (untimed)
     dobs = oracle.forward(og, mt, sample.src_pos(), sample.rec_pos(), sample.wavelet())
-    t0 = time.perf_counter()
-    if kind == "range_finder":
-        Q = oracle.range_finder_probes(dobs, r, sample.probe_seed)
-        oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind="explicit",
-                               r=r, Z=Q, scale=1.0)
-    else:
-        oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind=kind, r=r,
-                               seed=sample.probe_seed)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        if kind == "range_finder":
+            Q = oracle.range_finder_probes(dobs, r, sample.probe_seed)
+            oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs,
+                                   kind="explicit", r=r, Z=Q, scale=1.0)
+        else:
+            oracle.gradient_probed(og, m0, sample.src_pos(), sample.rec_pos(), sample.wavelet(), dobs, kind=kind,
+                                   r=r, seed=sample.probe_seed)
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
     upd = sample.nshots * sample.n_pad * 2 * (sample.nt - 1)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(upd / dt / 1e9, 5), "unit": "GPts/s", "cores": cores, "kind": "oracle",
-            "seconds": round(dt, 2),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "runs": reps, "statistic": "median",
+            "seconds": [round(t, 2) for t in times],
             "sample": "%d of %d shots, first %d of %d time steps, r=%d %s, same grid; FP64 C oracle with OpenMP"
                       % (sample.nshots, wl.nshots, sample.nt, wl.nt, r, kind)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def copy_bandwidth(dev, n: int = 1 << 28, reps: int = 5) -> float:

@@ -226,7 +226,10 @@ void tpx_job_destroy(tpx_job *job);
  * into the caller's stream before the pass ends (the ring then holds 2b + 3
  * instead of b + 2 slots).  The option changes workspace sizes: set it before
  * sizing a workspace, not between sizing and use. */
-enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2 };
+enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2, TPX_OPT_FUSED_STEPS_3D = 3 };
+/* TPX_OPT_FUSED_STEPS_3D (default 0): 3D launches advance two leapfrog steps
+ * at a time (as 2D launches always do) instead of one.  Results are bitwise
+ * the same either way; only speed differs. */
 /* TPX_OPT_MATRIX_CORES (default 1): the probe contractions of the time
  * blocks are dense products (r x b by b x points) and can run on the matrix
  * cores when r is a multiple of 16: bfloat16 MFMA with each FP32 field value

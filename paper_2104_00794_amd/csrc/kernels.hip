@@ -346,12 +346,51 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
 // ---------------------------------------------------------------------------
 constexpr int kBufNT = 2;   // cache-policy bit of a streamed (nontemporal) buffer access
 
+// Arguments of the 3D step kernels as one kernel parameter, so the step
+// arguments sit at a known offset of the kernel-argument segment.
+struct Step3DArgs {
+    Layout L;
+    Physics ph;
+    StepArgs a;
+};
+typedef const __attribute__((address_space(4))) StepArgs *KernargStep;
+
+// The step arguments read straight from the kernel-argument segment through a
+// pointer the compiler cannot see through: the source-injection tables are
+// rarely needed, and loading them only where they are used keeps them out of
+// the scalar registers of the march.
+__device__ __forceinline__ KernargStep kernarg_step_args() {
+    KernargStep p = (KernargStep)((const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr() +
+                                  offsetof(Step3DArgs, a));
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Source term of padded node (x, y, z) inside the box, looked up in the
+// injection map of the two-step kernel's tile that owns the node.
+template <int R>
+__device__ __forceinline__ float source_3d(const Layout &L, KernargStep ka, int shot, int x, int y, int z) {
+    constexpr int TX = t2x(R);
+    InjectTables inj;
+    inj.tile_dense = ka->inj.tile_dense;
+    inj.dense = ka->inj.dense;
+    inj.seg_ent = ka->inj.seg_ent;
+    inj.ent_idx = ka->inj.ent_idx;
+    inj.ent_w = ka->inj.ent_w;
+    inj.col_z = nullptr;
+    const int tx = x / TX, ty = y / T3Y2;
+    const int map = inj.tile_dense[(((int64_t)shot * L.ntiles[2] + z) * L.ntiles[1] + ty) * L.ntiles[0] + tx];
+    if (map < 0) return 0.0f;
+    const int sg = inj.dense[(int64_t)map * (64 * (T3Y2 + 2 * R)) + (y - ty * T3Y2 + R) * 64 + (x - tx * TX + R)];
+    const float *amp = ka->amp.ptr + shot * ka->amp.shot_stride + (int64_t)ka->k * ka->amp.k_stride;
+    return sg >= 0 ? segment_value(inj, amp, ka->amp.scale, sg) : 0.0f;
+}
+
 template <int R, bool FAST>
 __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot, int bx,
                                             int by, int zc, float (*plane_t)[T3Y + 2 * R][T3X + 2 * R]) {
 #pragma clang fp contract(off)
     constexpr int W = T3X + 2 * R;
-    const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
     const int lx = threadIdx.x & 63;
     const int ly = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int x0 = bx * T3X, y0 = by * T3Y, zc0 = zc * T3Z;
@@ -409,6 +448,15 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
     }
     float h[6];
     load_halo(zc0, h);
+    // planes with source nodes in the two-step kernel's tile columns this
+    // block overlaps (its 64 columns span at most two, its 8 rows one)
+    int zlo = 1, zhi = 0;
+    if (a.inject) {
+        const int ty = y0 / T3Y2, tx0 = x0 / t2x(R), tx1 = min(x0 + T3X - 1, P0 - 1) / t2x(R);
+        const int c0 = (shot * (int)L.ntiles[1] + ty) * (int)L.ntiles[0] + tx0, c1 = c0 + (tx1 - tx0);
+        zlo = __builtin_amdgcn_readfirstlane(min(a.inj.col_z[2 * c0], a.inj.col_z[2 * c1]));
+        zhi = __builtin_amdgcn_readfirstlane(max(a.inj.col_z[2 * c0 + 1], a.inj.col_z[2 * c1 + 1]));
+    }
     const float hx = FAST ? 0.0f : layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
     const float hxy_a = FAST ? 0.0f : hx + layer_frac2(ya, (int)L.n[1], L.nb, ph.inv_nb);
     const float hxy_b = FAST ? 0.0f : hx + layer_frac2(yb, (int)L.n[1], L.nb, ph.inv_nb);
@@ -451,15 +499,10 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
             pt[R + 4 + ly][hc] = h[5];
         }
         float sa = 0.0f, sbv = 0.0f;   // point-source terms of this thread's two nodes
-        if (a.inject) {
-            const int map = a.inj.tile_dense[(((int64_t)shot * L.ntiles[2] + z) * nty + by) * ntx + bx];
-            if (map >= 0) {
-                const int32_t *dm = a.inj.dense + (int64_t)map * (T3X * T3Y) + ly * T3X + lx;
-                const float *amp = a.amp.ptr + shot * a.amp.shot_stride + (int64_t)a.k * a.amp.k_stride;
-                const int ga = dm[0], gb = dm[4 * T3X];
-                if (ga >= 0) sa = segment_value(a.inj, amp, a.amp.scale, ga);
-                if (gb >= 0) sbv = segment_value(a.inj, amp, a.amp.scale, gb);
-            }
+        if (z >= zlo && z <= zhi) {
+            const KernargStep ka = kernarg_step_args();
+            if (oa) sa = source_3d<R>(L, ka, shot, x, ya, z);
+            if (ob) sbv = source_3d<R>(L, ka, shot, x, yb, z);
         }
         __syncthreads();
         if (lz + 1 < T3Z && (FAST || z + 1 < P2)) {   // prefetch, overlaps the compute below
@@ -497,9 +540,12 @@ __device__ __forceinline__ void step3d_body(const Layout &L, const Physics &ph, 
 }
 
 template <int R>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_step3d(const Layout L, const Physics ph, const StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_step3d(const Step3DArgs P) {
+    const Layout &L = P.L;
+    const Physics &ph = P.ph;
+    const StepArgs &a = P.a;
     __shared__ float plane_t[2][T3Y + 2 * R][T3X + 2 * R];
-    const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1];
+    const int ntx = (int)((L.P[0] + T3X - 1) / T3X), nty = (int)((L.P[1] + T3Y - 1) / T3Y);
     const int nzc = (int)((L.P[2] + T3Z - 1) / T3Z);
     const int lid = xcd_logical_block(ntx * nty * nzc * L.S);
     if (lid < 0) return;
@@ -508,12 +554,343 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     // interior column: every node undamped and every read inside the padded box
     const bool fast = x0 - R >= nb && x0 + T3X + R <= nb + (int)L.n[0] && y0 - R >= nb &&
                       y0 + T3Y + R <= nb + (int)L.n[1] && zc0 - R >= nb && zc0 + T3Z + R <= nb + (int)L.n[2];
-    if (fast) step3d_body<R, true>(L, ph, a, shot, bx, by, zc, plane_t);
-    else step3d_body<R, false>(L, ph, a, shot, bx, by, zc, plane_t);
-
+    // sampling first: the launch's inputs are read-only
     const int per_shot = ntx * nty * nzc, bis = (zc * nty + by) * ntx + bx;
     if (a.do_sample) sample_points<8>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bis, per_shot);
     if (a.sample_prev) sample_points<8>(L, a.prev + shot * L.shot_floats, a.kp, a.smp, shot, bis, per_shot);
+    if (fast) step3d_body<R, true>(L, ph, a, shot, bx, by, zc, plane_t);
+    else step3d_body<R, false>(L, ph, a, shot, bx, by, zc, plane_t);
+}
+
+// ---------------------------------------------------------------------------
+// 3D leapfrog, two steps per launch (temporal blocking along the z march).
+//
+// Block = 8 waves over a tile of T3Y2 rows (y) by TX = 64 - 2R columns (x);
+// lane l of every wave holds column x0 - R + l, so a wave row covers the tile
+// plus an R-wide x halo.  The tile plus an R-wide halo in x and y is the
+// extended region.  The block marches a z chunk of tz3 planes: at march
+// position p the first step gives u^{k+1} at plane z1 = zc0 - R + p on the
+// extended region, and the second step gives u^{k+2} at plane z2 = z1 - R on
+// the tile.  The second step lags R planes behind the first, so its z
+// neighbours are known when it runs.  Each thread owns two tile rows and (in
+// waves < 2R) one halo row of the extended region and keeps, in registers,
+//   u^k      a z queue of 2R + 1 planes per owned row,
+//   u^{k+1}  a z queue of 2R + 1 planes per owned tile row,
+//   beta     the last R + 1 planes per owned tile row (the second step's).
+// x/y neighbours come from LDS: u^k at plane z1 staged with a 2R halo around
+// the extended region (double-buffered), and the last R + 1 planes of u^{k+1}
+// on the extended region (a ring).  One barrier per plane.  u^{k-1}, u^k and
+// beta are read once for two steps; u^{k+1} and u^{k+2} are written on the
+// tile.  Halo nodes of u^{k+1} are recomputed by the neighbouring tiles and
+// chunks with the one-step kernel's arithmetic, so one launch of two steps
+// and two launches of one step give the same bits.
+// ---------------------------------------------------------------------------
+template <int N>
+struct Phase {
+    static constexpr int value = N;
+};
+
+template <int R, bool FAST>
+__device__ __forceinline__ void step3d2_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot, int bx,
+                                             int by, int zc0, int zend, float (*Us)[T3Y2 + 4 * R][64 + 2 * R],
+                                             float (*Vr)[T3Y2 + 2 * R][64 + 2 * R]) {
+#pragma clang fp contract(off)
+    constexpr int TX = t2x(R);
+    constexpr int EY = T3Y2 + 2 * R;   // rows of the extended region
+    constexpr int SY = T3Y2 + 4 * R;   // staged rows of u^k
+    constexpr int NV = R + 1;          // planes of u^{k+1} held in LDS
+    constexpr int NQ = 2 * R + 1;      // planes held by a z queue
+    constexpr int MAPN = 64 * EY;      // nodes of one plane's injection map
+    const int lx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int x0 = bx * TX, y0 = by * T3Y2;
+    const int x = x0 - R + lx;
+    const bool hrow = w < 2 * R;   // this wave owns a halo row of the extended region
+    // owned rows of the extended region: two tile rows, then the halo row
+    const int er[3] = {R + w, R + 8 + w, w < R ? w : T3Y2 + w};
+    const int G0 = (int)L.G[0], PL = (int)(L.G[0] * L.G[1]);
+    const int P0 = (int)L.P[0], P1 = (int)L.P[1], P2 = (int)L.P[2], oy = (int)L.oy;
+    const uint32_t span = (uint32_t)(L.shot_floats * 4);
+    const int64_t so = shot * L.shot_floats + XO;
+    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cur + so, span), rp = buf_rsrc(a.prev + so, span);
+    const __amdgpu_buffer_rsrc_t rb = buf_rsrc(a.beta + XO, span);
+    const __amdgpu_buffer_rsrc_t rn1 = buf_rsrc(a.next + so, span), rn2 = buf_rsrc(a.next2 + so, span);
+    auto plane = [&](int z) { return (uint32_t)((FAST ? z : clampi(z, 0, P2 - 1)) + R) * (uint32_t)PL * 4u; };
+    auto lane = [&](int y, int xx) {   // byte offset of (y, x) within a plane
+        return 4u * (uint32_t)(((FAST ? y : clampi(y, 0, P1 - 1)) + oy) * G0 + (FAST ? xx : clampi(xx, 0, P0 - 1)));
+    };
+    auto zin = [&](int z) { return FAST || (z >= 0 && z < P2); };
+
+    // this lane's node in each owned row
+    const bool xin = FAST || (x >= 0 && x < P0);
+    const bool act = lx >= R && lx < R + TX;   // tile columns
+    uint32_t vo[3];
+    bool rin[3];
+    float hxy[3];
+    const float hx = FAST ? 0.0f : layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int y = y0 - R + er[i];
+        vo[i] = lane(y, x);
+        rin[i] = (i < 2 || hrow) && (FAST || (xin && y >= 0 && y < P1));
+        hxy[i] = FAST ? 0.0f : hx + layer_frac2(y, (int)L.n[1], L.nb, ph.inv_nb);
+    }
+    // the staged plane's x halo of each owned row (lanes < 2R): staged column scx
+    const bool xl = lx < 2 * R;
+    const int scx = lx < R ? lx : 64 + lx;
+    const int xc = x0 - 2 * R + scx;
+    uint32_t co[3];
+    bool cin[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int y = y0 - R + er[i];
+        co[i] = lane(y, xl ? xc : x);
+        cin[i] = xl && (i < 2 || hrow) && (FAST || (xc >= 0 && xc < P0 && y >= 0 && y < P1));
+    }
+    // the staged plane's y halo: staged row xr (waves < 2R), columns lx and 64 + lx (lanes < 2R)
+    const int xr = w < R ? w : SY - 2 * R + w;
+    const int yr = y0 - 2 * R + xr;
+    const int xa = x0 - 2 * R + lx, xb = x0 + TX + lx;
+    const bool yrin = FAST || (yr >= 0 && yr < P1);
+    const bool rain = hrow && yrin && (FAST || (xa >= 0 && xa < P0));
+    const bool rbin = hrow && xl && yrin && (FAST || xb < P0);
+    const uint32_t ra = lane(yr, xa), rbo = lane(yr, xl ? xb : xa);
+
+    // z queues indexed by plane modulo NQ: the march position p holds the
+    // first step at plane z1 = zc0 - R + p, and plane z1 + d sits in slot
+    // (p + d) mod NQ.  The march is unrolled NQ times, so every slot index is
+    // a constant and no value moves between registers.
+    float qk[3][NQ], qv[2][NQ];
+#pragma unroll
+    for (int j = 0; j < 2 * R; ++j) {   // u^k at planes z1 - R .. z1 + R - 1 of position 0
+        const int z = zc0 - 2 * R + j;
+        const uint32_t zo = plane(z);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float v = 0.0f;
+            if (i < 2 || hrow) v = buf_load(rc, vo[i], zo);
+            qk[i][(j - R + NQ) % NQ] = (rin[i] && zin(z)) ? v : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+        for (int j = 0; j < NQ; ++j) qv[t][j] = 0.0f;
+    }
+
+    // loads of one march position, issued one plane ahead: u^k at z1 + R and
+    // the staged plane's halo at z1, u^{k-1} and beta at z1, beta at z1 - R
+    // for the second step (tile rows; read R planes ago, so a cache hit)
+    float nk[3], nc[3], np_[3], nbt[3], nr[2], nb2[2];
+    auto load_plane = [&](int z1) {
+        const uint32_t zo = plane(z1), zq = plane(z1 + R), zb2 = plane(z1 - R);
+        nb2[0] = buf_load(rb, vo[0], zb2);
+        nb2[1] = buf_load(rb, vo[1], zb2);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i < 2 || hrow) {
+                nk[i] = buf_load(rc, vo[i], zq);
+                nc[i] = buf_load(rc, co[i], zo);
+                np_[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rp, (int)vo[i], (int)zo, kBufNT));
+                nbt[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, (int)vo[i], (int)zo, kBufNT));
+            } else {
+                nk[i] = nc[i] = np_[i] = nbt[i] = 0.0f;
+            }
+        }
+        if (hrow) {
+            nr[0] = buf_load(rc, ra, zo);
+            nr[1] = buf_load(rc, rbo, zo);
+        } else {
+            nr[0] = nr[1] = 0.0f;
+        }
+    };
+    load_plane(zc0 - R);
+
+    const int niter = (zend - zc0) + 2 * R;
+    // planes of this tile column that hold source nodes (none: zlo > zhi)
+    int zlo = 1, zhi = 0;
+    if (a.inject) {
+        const int col = (shot * (int)L.ntiles[1] + by) * (int)L.ntiles[0] + bx;
+        zlo = __builtin_amdgcn_readfirstlane(a.inj.col_z[2 * col]);
+        zhi = __builtin_amdgcn_readfirstlane(a.inj.col_z[2 * col + 1]);
+    }
+
+    // one march position; PH = p mod NQ
+    auto position = [&](auto phase, int p) __attribute__((always_inline)) {
+        constexpr int PH = decltype(phase)::value;
+        auto sk = [](int d) { return (PH + d + 2 * NQ) % NQ; };   // slot of plane z1 + d
+        const int z1 = zc0 - R + p, z2 = z1 - R;
+        const bool z1in = zin(z1);
+        const bool two = p >= 2 * R;   // the second step runs at z2
+        // take the loads of this position
+        float pm[3], bt[3], b2[2] = {nb2[0], nb2[1]};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            qk[i][sk(R)] = (rin[i] && zin(z1 + R)) ? nk[i] : 0.0f;
+            pm[i] = np_[i];
+            bt[i] = nbt[i];
+        }
+        float(*U)[64 + 2 * R] = Us[p & 1];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i < 2 || hrow) {
+                U[er[i] + R][lx + R] = qk[i][sk(0)];
+                if (xl) U[er[i] + R][scx] = (cin[i] && z1in) ? nc[i] : 0.0f;
+            }
+        }
+        if (hrow) {
+            U[xr][lx] = (rain && z1in) ? nr[0] : 0.0f;
+            if (xl) U[xr][64 + lx] = (rbin && z1in) ? nr[1] : 0.0f;
+        }
+        // point-source terms: the first step's on the extended region at z1,
+        // the second step's on the tile at z2
+        float s1[3] = {0.0f, 0.0f, 0.0f}, s2[2] = {0.0f, 0.0f};
+        if (zlo <= zhi && ((z1 >= zlo && z1 <= zhi) || (two && z2 >= zlo && z2 <= zhi))) {
+            const KernargStep ka = kernarg_step_args();
+            InjectTables inj;
+            inj.tile_dense = ka->inj.tile_dense;
+            inj.dense = ka->inj.dense;
+            inj.seg_ent = ka->inj.seg_ent;
+            inj.ent_idx = ka->inj.ent_idx;
+            inj.ent_w = ka->inj.ent_w;
+            inj.col_z = nullptr;
+            const float *amp0 = ka->amp.ptr + shot * ka->amp.shot_stride;
+            const float scale = ka->amp.scale;
+            const int64_t col_planes = (int64_t)shot * L.ntiles[2];
+            if (z1 >= zlo && z1 <= zhi) {
+                const int map = inj.tile_dense[((col_planes + z1) * L.ntiles[1] + by) * L.ntiles[0] + bx];
+                if (map >= 0) {
+                    const float *amp1 = amp0 + (int64_t)ka->k * ka->amp.k_stride;
+                    const int32_t *dm = inj.dense + (int64_t)map * MAPN + lx;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        if (i < 2 || hrow) {
+                            const int sg = dm[er[i] * 64];
+                            if (sg >= 0) s1[i] = segment_value(inj, amp1, scale, sg);
+                        }
+                    }
+                }
+            }
+            if (two && z2 >= zlo && z2 <= zhi) {
+                const int map = inj.tile_dense[((col_planes + z2) * L.ntiles[1] + by) * L.ntiles[0] + bx];
+                if (map >= 0) {
+                    const float *amp2 = amp0 + (int64_t)ka->k2 * ka->amp.k_stride;
+                    const int32_t *dm = inj.dense + (int64_t)map * MAPN + lx;
+#pragma unroll
+                    for (int t = 0; t < 2; ++t) {
+                        const int sg = dm[er[t] * 64];
+                        if (sg >= 0) s2[t] = segment_value(inj, amp2, scale, sg);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (p + 1 < niter) load_plane(z1 + 1);   // overlaps the compute below
+
+        // first step at z1 on the owned rows of the extended region
+        const float hz1 = FAST ? 0.0f : layer_frac2(z1, (int)L.n[2], L.nb, ph.inv_nb);
+        const bool out1 = z1 >= zc0 && z1 < zend;   // u^{k+1} of this plane belongs to the chunk
+        const uint32_t zo1 = plane(z1);
+        float(*Vw)[64 + 2 * R] = Vr[p % NV];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            if (i < 2 || hrow) {
+                const int sr = er[i] + R, sc = lx + R;
+                const float cv = qk[i][sk(0)];
+                float lap = 3.0f * ph.c[0] * cv;
+#pragma unroll
+                for (int k = 1; k <= R; ++k)
+                    lap = __builtin_fmaf(ph.c[k], (U[sr][sc - k] + U[sr][sc + k]) + (U[sr - k][sc] + U[sr + k][sc]) +
+                                                      (qk[i][sk(-k)] + qk[i][sk(k)]),
+                                         lap);
+                float v;
+                if (FAST) {
+                    v = leapfrog0(cv, pm[i], bt[i], lap, s1[i]);
+                } else {
+                    v = (rin[i] && z1in) ? leapfrog(cv, pm[i], bt[i], lap, s1[i], ph.hd_max * (hxy[i] + hz1)) : 0.0f;
+                }
+                Vw[er[i]][lx + R] = v;
+                if (i < 2) {
+                    qv[i][sk(0)] = v;
+                    if (act && out1 && rin[i]) buf_store(v, rn1, vo[i], zo1);
+                }
+            }
+        }
+        // second step at z2 on the owned tile rows; the u^{k+1} plane z2 was
+        // written R positions ago, before this position's barrier
+        if (two) {
+            const float(*V)[64 + 2 * R] = Vr[(p - R) % NV];
+            const float hz2 = FAST ? 0.0f : layer_frac2(z2, (int)L.n[2], L.nb, ph.inv_nb);
+            const uint32_t zo2 = plane(z2);
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const int vr = er[t], vc = lx + R;   // idle lanes read the pad columns
+                const float cv = qv[t][sk(-R)];
+                float lap = 3.0f * ph.c[0] * cv;
+#pragma unroll
+                for (int k = 1; k <= R; ++k)
+                    lap = __builtin_fmaf(ph.c[k], (V[vr][vc - k] + V[vr][vc + k]) + (V[vr - k][vc] + V[vr + k][vc]) +
+                                                      (qv[t][sk(-R - k)] + qv[t][sk(-R + k)]),
+                                         lap);
+                const float u2 = FAST ? leapfrog0(cv, qk[t][sk(-R)], b2[t], lap, s2[t])
+                                      : leapfrog(cv, qk[t][sk(-R)], b2[t], lap, s2[t], ph.hd_max * (hxy[t] + hz2));
+                if (act && rin[t]) buf_store(u2, rn2, vo[t], zo2);
+            }
+        }
+    };
+
+    for (int p = 0; p < niter; p += NQ) {
+        position(Phase<0>{}, p);
+        if (p + 1 >= niter) break;
+        position(Phase<1>{}, p + 1);
+        if (p + 2 >= niter) break;
+        position(Phase<2>{}, p + 2);
+        if (p + 3 >= niter) break;
+        position(Phase<3>{}, p + 3);
+        if (p + 4 >= niter) break;
+        position(Phase<4>{}, p + 4);
+        if constexpr (NQ > 5) {
+            if (p + 5 >= niter) break;
+            position(Phase<5 % NQ>{}, p + 5);
+            if (p + 6 >= niter) break;
+            position(Phase<6 % NQ>{}, p + 6);
+            if (p + 7 >= niter) break;
+            position(Phase<7 % NQ>{}, p + 7);
+            if (p + 8 >= niter) break;
+            position(Phase<8 % NQ>{}, p + 8);
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_step3d2(const Step3DArgs P) {
+    constexpr int TX = t2x(R);
+    const Layout &L = P.L;
+    const Physics &ph = P.ph;
+    const StepArgs &a = P.a;
+    __shared__ float Us[2][T3Y2 + 4 * R][64 + 2 * R];
+    __shared__ float Vr[R + 1][T3Y2 + 2 * R][64 + 2 * R];   // R pad columns each side
+    const int ntx = (int)L.ntiles[0], nty = (int)L.ntiles[1], tz = L.tz3;
+    const int P0 = (int)L.P[0], P1 = (int)L.P[1], P2 = (int)L.P[2];
+    const int nzc = (P2 + tz - 1) / tz;
+    const int lid = xcd_logical_block(ntx * nty * nzc * L.S);
+    if (lid < 0) return;
+    const int bx = lid % ntx, by = (lid / ntx) % nty, zc = (lid / (ntx * nty)) % nzc, shot = lid / (ntx * nty * nzc);
+    const int x0 = bx * TX, y0 = by * T3Y2, zc0 = zc * tz, nb = L.nb;
+    const int zend = zc0 + tz < P2 ? zc0 + tz : P2;
+    // interior block: every staged read inside the padded box, every node of
+    // the extended region undamped at every plane of the first step
+    const bool fast = x0 - 2 * R >= 0 && x0 + TX + 2 * R <= P0 && y0 - 2 * R >= 0 && y0 + T3Y2 + 2 * R <= P1 &&
+                      zc0 - 2 * R >= 0 && zc0 + tz + 2 * R <= P2 && x0 - R >= nb && x0 + TX + R <= nb + (int)L.n[0] &&
+                      y0 - R >= nb && y0 + T3Y2 + R <= nb + (int)L.n[1] && zc0 - R >= nb &&
+                      zc0 + tz + R <= nb + (int)L.n[2];
+    // sampling first: the launch's inputs are read-only, and its arguments
+    // are dead before the march starts
+    const int per_shot = ntx * nty * nzc, bis = (zc * nty + by) * ntx + bx;
+    if (a.do_sample) sample_points<8>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bis, per_shot);
+    if (a.sample_prev) sample_points<8>(L, a.prev + shot * L.shot_floats, a.kp, a.smp, shot, bis, per_shot);
+    if (fast) step3d2_body<R, true>(L, ph, a, shot, bx, by, zc0, zend, Us, Vr);
+    else step3d2_body<R, false>(L, ph, a, shot, bx, by, zc0, zend, Us, Vr);
 }
 
 template <int NC>
@@ -543,13 +920,22 @@ hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hi
             else TPX_STEP2D(4, 1);
         }
 #undef TPX_STEP2D
+    } else if (a.nstep == 2) {
+        if (L.tz3 < 1 || L.tile[0] != t2x(L.R) || L.tile[1] != T3Y2) return hipErrorInvalidValue;
+        const int64_t zchunks = (L.P[2] + L.tz3 - 1) / L.tz3;
+        const int64_t nlog = L.ntiles[0] * L.ntiles[1] * zchunks * L.S;
+        dim3 grid((unsigned)((nlog + 7) / 8 * 8));
+        const Step3DArgs p3 = {L, ph, a};
+        if (L.R == 2) hipLaunchKernelGGL(k_step3d2<2>, grid, dim3(512), 0, stream, p3);
+        else hipLaunchKernelGGL(k_step3d2<4>, grid, dim3(512), 0, stream, p3);
     } else {
         if (a.nstep != 1) return hipErrorInvalidValue;
         const int64_t zchunks = (L.P[2] + T3Z - 1) / T3Z;
-        const int64_t nlog = L.ntiles[0] * L.ntiles[1] * zchunks * L.S;
+        const int64_t nlog = ((L.P[0] + T3X - 1) / T3X) * ((L.P[1] + T3Y - 1) / T3Y) * zchunks * L.S;
         dim3 grid((unsigned)((nlog + 7) / 8 * 8));
-        if (L.R == 2) hipLaunchKernelGGL(k_step3d<2>, grid, dim3(256), 0, stream, L, ph, a);
-        else hipLaunchKernelGGL(k_step3d<4>, grid, dim3(256), 0, stream, L, ph, a);
+        const Step3DArgs p3 = {L, ph, a};
+        if (L.R == 2) hipLaunchKernelGGL(k_step3d<2>, grid, dim3(256), 0, stream, p3);
+        else hipLaunchKernelGGL(k_step3d<4>, grid, dim3(256), 0, stream, p3);
     }
     return hipGetLastError();
 }

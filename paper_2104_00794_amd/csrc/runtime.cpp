@@ -190,12 +190,25 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
         L.map[0] = 64; L.map[1] = 1; L.map[2] = tz + 2 * L.R;
         L.map_org[0] = -L.R; L.map_org[1] = 0; L.map_org[2] = -L.R;
     } else {
-        L.tile[0] = T3X; L.tile[1] = T3Y; L.tile[2] = 1;
-        L.map[0] = T3X; L.map[1] = T3Y; L.map[2] = 1;
-        L.map_org[0] = L.map_org[1] = L.map_org[2] = 0;
+        // tiles of the two-step kernel, one plane deep; the map of a tile's
+        // plane covers the extended region the kernel's first step computes
+        L.tile[0] = t2x(L.R); L.tile[1] = T3Y2; L.tile[2] = 1;
+        L.map[0] = 64; L.map[1] = T3Y2 + 2 * L.R; L.map[2] = 1;
+        L.map_org[0] = -L.R; L.map_org[1] = -L.R; L.map_org[2] = 0;
     }
     for (int a = 0; a < 3; ++a) L.ntiles[a] = (L.P[a] + L.tile[a] - 1) / L.tile[a];
     L.tiles_per_shot = L.ntiles[0] * L.ntiles[1] * L.ntiles[2];
+    L.tz3 = 0;
+    if (L.ndim == 3) {
+        // z chunks of the two-step kernel: about 32 planes, shorter when the
+        // launch would otherwise hold fewer than 2048 blocks (8 per CU), never
+        // under 8 planes; chunks of one column get equal lengths
+        const int64_t cols = L.ntiles[0] * L.ntiles[1] * L.S;
+        int64_t nzc = (L.P[2] + 31) / 32;
+        const int64_t nzc_max = std::max<int64_t>(1, L.P[2] / 8);
+        while (nzc < nzc_max && cols * nzc < 2048) ++nzc;
+        L.tz3 = (int)((L.P[2] + nzc - 1) / nzc);
+    }
 
     double c[5];
     stencil_weights(g->space_order, c);
@@ -264,7 +277,7 @@ struct Blob {
 };
 
 struct HostInject {  // offsets into the blob
-    size_t tile_dense, dense, seg_ent, ent_idx, ent_w;
+    size_t tile_dense, dense, seg_ent, ent_idx, ent_w, col_z;
 };
 struct HostSample {
     size_t base, w;
@@ -310,7 +323,21 @@ HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
         ent_w.push_back(ent[i].w);
     }
     seg_ent.push_back((int32_t)ent.size());
+    // 3D: the first and last plane holding a map, per tile column (shot, y, x)
+    const int64_t ncol = L.ndim == 3 ? (int64_t)L.S * L.ntiles[0] * L.ntiles[1] : 0;
+    std::vector<int32_t> col_z(2 * ncol);
+    for (int64_t c = 0; c < ncol; ++c) {
+        col_z[2 * c] = INT32_MAX;
+        col_z[2 * c + 1] = -1;
+    }
+    for (size_t i = 0; i < ent.size() && ncol; ++i) {
+        const int64_t t = ent[i].tile, cxy = L.ntiles[0] * L.ntiles[1];
+        const int64_t z = (t / cxy) % L.ntiles[2], c = (t / (cxy * L.ntiles[2])) * cxy + t % cxy;
+        col_z[2 * c] = std::min<int32_t>(col_z[2 * c], (int32_t)z);
+        col_z[2 * c + 1] = std::max<int32_t>(col_z[2 * c + 1], (int32_t)z);
+    }
     HostInject h;
+    h.col_z = b.put(col_z.data(), col_z.size() * 4);
     h.tile_dense = b.put(tile_dense.data(), tile_dense.size() * 4);
     h.dense = b.put(dense.data(), dense.size() * 4);
     h.seg_ent = b.put(seg_ent.data(), seg_ent.size() * 4);
@@ -414,6 +441,8 @@ std::atomic<int> g_overlap{0};
 // ubar and vbar for r >= 64; 2 every contraction whenever the probes qualify
 // (a kind exact in bfloat16 and r a multiple of 16).
 std::atomic<int> g_mfma{1};
+// Two fused leapfrog steps per 3D launch (2D launches always fuse two).
+std::atomic<int> g_fused3d{0};
 
 // Auxiliary streams, created on first use and kept for the process lifetime.
 std::mutex g_aux_mu;
@@ -438,17 +467,21 @@ void aux_release(hipStream_t s) {
 // stream order; 2 b + 3 when a block's contraction overlaps the next block.
 int ring_slots(int b, bool overlap) { return overlap ? 2 * b + 3 : b + 2; }
 
-// Time steps buffered per probe contraction: the accumulators' read-modify-
+// Time steps buffered per probe contraction.  The accumulators' read-modify-
 // write costs 8 r / b bytes per point-step against the 4 bytes of the ring
-// read, and the ring costs ring_slots(b) slots.  b starts at 16 r (the
-// accumulator traffic at an eighth of the ring's), within 256 .. 1024, and is
-// halved while the ring exceeds 80 GB (under 30% of the GPU's 288 GB).
+// read, and the ring holds ring_slots(b) wavefield levels.  b starts at 16 r
+// (the accumulator traffic at an eighth of the ring's), within 256 .. 1024.
+// It is then lowered, in steps of 16 levels, until the ring takes at most
+// max(6 x the accumulators, 8 GB): the probed workspace stays a small multiple
+// of the r x N accumulators the method keeps, instead of growing with the
+// grid to a large share of the GPU's memory.
 int default_block(const Layout &L, int nt, bool overlap, int r) {
     const double slot_bytes = (double)L.slot_floats * 4.0;
-    const double cap = 80e9;
+    const double acc_bytes = (double)L.S * r * L.nphys * 4.0;
+    const double cap = std::max(6.0 * acc_bytes, 8e9);
     int b = 256;
     while (b < 1024 && b < 16 * r) b *= 2;
-    while (b > 16 && ring_slots(b, overlap) * slot_bytes > cap) b /= 2;
+    while (b > 16 && ring_slots(b, overlap) * slot_bytes > cap) b -= 16;
     if (b > nt - 1) b = nt - 1;
     if (b < 1) b = 1;
     return b;
@@ -519,10 +552,10 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     p.block = default_block(L, P.nt, p.overlap, r);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
-    // without contractions the ring holds the levels one launch touches: three,
-    // four for two fused steps (2D).  With contractions a launch never crosses a
-    // block end, so one block plus two levels suffices.
-    p.nslots = plain ? (P.L.ndim == 2 ? 4 : 3) : ring_slots(p.block, p.overlap);
+    // without contractions the ring holds the four levels a launch of two
+    // fused steps touches.  With contractions a launch never crosses a block
+    // end, so one block plus two levels suffices.
+    p.nslots = plain ? 4 : ring_slots(p.block, p.overlap);
     const size_t slot = (size_t)L.slot_floats * 4;
     const size_t ntr = (size_t)L.S * P.nt * P.nrec;
     size_t o = 0;
@@ -619,6 +652,7 @@ tpx_status overlap_join(Ctx &C, int nblocks) {
 InjectTables dev_inject(unsigned char *base, const HostInject &h) {
     InjectTables t;
     t.tile_dense = (const int32_t *)(base + h.tile_dense);
+    t.col_z = (const int32_t *)(base + h.col_z);
     t.dense = (const int32_t *)(base + h.dense);
     t.seg_ent = (const int32_t *)(base + h.seg_ent);
     t.ent_idx = (const int32_t *)(base + h.ent_idx);
@@ -775,10 +809,10 @@ struct FwdLoop {
     bool finished = false;
 };
 
-// Two fused steps are used in 2D whenever both steps fall in the caller's
-// budget and in one contraction block (the ring holds one block plus the two
-// levels around it).  They are skipped when contractions overlap the steps.
-bool two_steps_allowed(const Ctx &C) { return C.P.L.ndim == 2 && !C.plan.overlap; }
+// Two fused steps are used whenever both steps fall in the caller's budget
+// and in one contraction block (the ring holds one block plus the two levels
+// around it).  They are skipped when contractions overlap the steps.
+bool two_steps_allowed(const Ctx &C) { return !C.plan.overlap && (C.P.L.ndim == 2 || g_fused3d.load() != 0); }
 
 tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
                      float *ubar, int dtt = 0) {
@@ -1457,6 +1491,10 @@ tpx_status tpx_set_option(int32_t option, int64_t value) {
         g_overlap.store(value ? 1 : 0);
         return TPX_OK;
     }
+    if (option == TPX_OPT_FUSED_STEPS_3D) {
+        g_fused3d.store(value ? 1 : 0);
+        return TPX_OK;
+    }
     if (option == TPX_OPT_MATRIX_CORES) {
         if (value < 0 || value > 2) return fail(TPX_E_INVAL, "TPX_OPT_MATRIX_CORES takes 0, 1 or 2");
         g_mfma.store((int)value);
@@ -1468,6 +1506,7 @@ tpx_status tpx_set_option(int32_t option, int64_t value) {
 int64_t tpx_get_option(int32_t option) {
     if (option == TPX_OPT_OVERLAP_CONTRACTIONS) return g_overlap.load();
     if (option == TPX_OPT_MATRIX_CORES) return g_mfma.load();
+    if (option == TPX_OPT_FUSED_STEPS_3D) return g_fused3d.load();
     return -1;
 }
 

@@ -34,10 +34,14 @@ constexpr int T2Z = 32;
 constexpr int T2Z_MID = 16;
 constexpr int T2Z_SMALL = 8;
 __host__ __device__ constexpr int t2x(int R) { return 64 - 2 * R; }
-// 3D step kernel tile: 64 (x) by 8 (y) columns, marching T3Z planes in z.
+// One-step 3D kernel: blocks of 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
 constexpr int T3Y = 8;
 constexpr int T3Z = 12;
+// Two-step 3D kernel, whose tiles also key the 3D injection tables: T3Y2 rows
+// (y) by 64 - 2R columns (x), so one wave row spans the tile plus an R-wide
+// halo on each side; eight waves; z chunks of Layout::tz3 planes.
+constexpr int T3Y2 = 16;
 
 struct Layout {
     int ndim;      // 2 or 3
@@ -55,9 +59,11 @@ struct Layout {
     // tiles of the step kernel (used by the injection tables)
     int tile[3];
     int64_t ntiles[3];
+    int tz3;              // 3D: planes per z chunk of the two-step kernel
     int64_t tiles_per_shot;
     // injection map of one tile: extents and origin relative to the tile's
-    // first node (2D: 64 x (T2Z + 2R) nodes from (-R, -R); 3D: the tile)
+    // first node (2D: 64 x (T2Z + 2R) nodes from (-R, -R); 3D, per plane:
+    // 64 x (T3Y2 + 2R) nodes from (-R, -R))
     int map[3];
     int map_org[3];
 
@@ -85,6 +91,7 @@ struct InjectTables {
     const int32_t *seg_ent;    // [nseg + 1] entry ranges
     const int32_t *ent_idx;    // [nent] source index (receiver id or 0)
     const float *ent_w;        // [nent] interpolation weight
+    const int32_t *col_z;      // 3D: [S * ntiles_y * ntiles_x][2] first and last plane with a map (empty: lo > hi)
 };
 
 // Amplitudes injected at step k: amp[shot * shot_stride + k * k_stride + idx] * scale
@@ -115,7 +122,7 @@ struct StepArgs {
     float *next;        // u^{k+1}
     float *next2;       // u^{k+2} (two-step launches only)
     const float *beta;  // dt^2 / m_pad, one shot-sized field
-    int nstep;          // 1 or 2 (two steps: 2D only)
+    int nstep;          // 1 or 2
     int k;              // time index of `cur`: amplitudes of the first step, sample row of `cur`
     int k2;             // amplitude index of the second step
     int kp;             // time index of `prev` (its sample row)

@@ -16,8 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# TPX_LIBRARY may point at another build of the same library (e.g. a tuning build)
-LIB_PATH = os.environ.get("TPX_LIBRARY") or os.path.join(_HERE, "_build", "libtpx.so")
+LIB_PATH = os.path.join(_HERE, "_build", "libtpx.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "tpx.h")
 
 OK, E_INVAL, E_CFL, E_GEOM, E_NOMEM, E_DEVICE, E_NUMERIC, E_STATE = range(8)
@@ -444,6 +443,7 @@ class Job:
 KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL, KERNEL_STEP2 = range(5)
 OPT_OVERLAP_CONTRACTIONS = 1
 OPT_MATRIX_CORES = 2
+OPT_FUSED_STEPS_3D = 3
 
 
 def set_option(option: int, value: int):

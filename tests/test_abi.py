@@ -86,7 +86,11 @@ def test_full_history_of_3d_config_exceeds_one_gpu():
     full = tpx.workspace_bytes(tpx.CALL_GRADIENT_FULL, grid, geom)
     probed = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=32))
     assert full > 288e9
-    assert probed < 0.35 * 288e9   # a 256-level ring (78 GB) and the accumulators
+    # the ring is capped at six times the 6.2 GB of accumulators (a 112-level
+    # block, 34 GB): the probed workspace stays under 45 GB, a sixth of the GPU
+    assert probed < 45e9
+    hist = 401 * 401 * 301 * 2001 * 4.0   # the N x n_t history of Eq. 3
+    assert hist / probed > 8.5
 
 
 def test_probe_side_validated():

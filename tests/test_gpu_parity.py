@@ -659,6 +659,50 @@ def test_one_and_two_step_launches_are_bitwise_identical():
     assert rel_l2(to_np(g2), g_o) <= 1e-4
 
 
+@pytest.mark.parametrize("order", [8, 4])
+def test_3d_one_and_two_step_launches_are_bitwise_identical(order):
+    import torch
+
+    # 3D: a job advanced one time step per call runs only the one-step kernel;
+    # with fused 3D steps switched on, the gradient call and the plain forward
+    # run the two-step kernel (tiles of 16 rows, z chunks of 9 planes here,
+    # interior blocks on the fast path, an odd record leaving one single step
+    # per pass).  Same bits both ways, and the same as with the option off.
+    print("[case] one-step vs two-step launches, 3D, order", order, flush=True)
+    wl = small_3d(nz=60, ny=40, nx=130, nt=81, nbl=5, nshots=2, nrec=23, order=order)
+    # receivers straddling x and y tile edges (x = 56, y = 16 padded nodes)
+    rec = [(h * (56 - 5 - 1.5 + 0.7 * i), h * (16 - 5 - 0.5 + 0.45 * i), 0.12 * 59 * h) for i in range(8)
+           for h in (wl.h,)]
+    wl = wl.with_(rec=rec + [tuple(r) for r in wl.rec[:15]])
+    c = Case(wl)
+    dobs = c.dobs_oracle()
+    m0, d = cuda(c.m0), cuda(dobs)
+    probe = tpx.Probe(r=8, seed=5, block=16)
+    try:
+        tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 1)
+        d_two = tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true))
+        g2, J2 = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m0, d)
+        gf2, Jf2 = tpx.gradient_full(c.tgrid(), c.tgeom(), m0, d)
+        job = tpx.Job(c.tgrid(), c.tgeom(), probe, m0, d)
+        while not job.advance(1):
+            pass
+        tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 0)
+        d_one = tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true))
+        g1, J1 = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m0, d)
+        torch.cuda.synchronize()
+    finally:
+        tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 0)
+    assert rel_l2(to_np(d_two), dobs) <= TOL
+    assert torch.equal(d_one, d_two)
+    assert torch.equal(job.g, g2) and torch.equal(job.J, J2)
+    assert torch.equal(g1, g2) and torch.equal(J1, J2)
+    g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=8, seed=5)
+    assert rel_l2(to_np(g2), g_o) <= TOL
+    assert abs(float(J2.item()) - J_o) <= TOL * J_o
+    gf_o, _ = oracle.gradient_full(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs)
+    assert rel_l2(to_np(gf2), gf_o) <= TOL
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 @pytest.mark.parametrize("keep_vbar", [False, True])
 def test_algorithm1_side_matches_oracle(ndim, keep_vbar):

@@ -10,9 +10,8 @@ PKG = os.path.join(ROOT, "paper_2104_00794_amd")
 
 
 def test_missing_library_raises():
-    code = ("import os\n"
-            "os.environ['TPX_LIBRARY'] = '/nonexistent/libtpx.so'\n"
-            "from paper_2104_00794_amd import tpx\n"
+    code = ("from paper_2104_00794_amd import tpx\n"
+            "tpx.LIB_PATH = '/nonexistent/libtpx.so'\n"
             "try:\n"
             "    tpx.lib()\n"
             "except RuntimeError as e:\n"
