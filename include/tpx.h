@@ -185,6 +185,26 @@ tpx_status tpx_gradient_probed(const tpx_grid *grid, const tpx_geom *geom, const
                                const float *m, const float *d_obs, float *g, double *J, float *d_out,
                                void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the probed
+ * gradient of tpx_gradient_probed, with the same arguments and results, but
+ * no workspace argument.  Its workspace is a static device array of the
+ * library, TPX_NOALLOC_SCRATCH_BYTES (64 MiB) on each GPU, held until the
+ * process ends; the call neither allocates nor frees memory.  Problems whose
+ * probed workspace exceeds that size (tpx_workspace_bytes with
+ * TPX_CALL_GRADIENT_PROBED and the contraction-overlap option off) return
+ * TPX_E_NOMEM before any launch.  The geometry tables are copied from pageable
+ * host memory and the call waits for that copy (hipStreamSynchronize on
+ * `stream`), so, unlike the other calls, it does wait for the stream once;
+ * contractions always run in stream order.  Every call on one GPU shares that
+ * GPU's array and leaves its contents behind (each call initialises what it
+ * reads): calls that overlap in time on one GPU race and give wrong results,
+ * so serialise them (one stream, or one call at a time). */
+#define TPX_NOALLOC_SCRATCH_BYTES (64u << 20)
+tpx_status tpx_gradient_probed_noalloc(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe,
+                                       const float *m, const float *d_obs, float *g, double *J, float *d_out,
+                                       void *stream);
+
 /* Exact gradient (Eq. 3) from the stored forward history (N x nt values):
  * the conventional reference path.  Returns TPX_E_NOMEM when the history does
  * not fit the workspace. */

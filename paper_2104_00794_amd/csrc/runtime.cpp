@@ -534,7 +534,7 @@ tpx_status check_probe(const Problem &P, const tpx_probe *pr) {
     return TPX_OK;
 }
 
-Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_bytes) {
+Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_bytes, bool allow_overlap = true) {
     const Layout &L = P.L;
     Plan p;
     memset(&p, 0, sizeof p);
@@ -548,7 +548,7 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     const bool probed = mode == M_GRAD_PROBED || mode == M_FWD_PROBED || mode == M_BWD_PROBED;
     const int r = probed ? pr->r : 0;
     const bool plain = mode == M_FORWARD || mode == M_ADJOINT || mode == M_OBJECTIVE;
-    p.overlap = g_overlap.load() != 0 && !plain;
+    p.overlap = allow_overlap && g_overlap.load() != 0 && !plain;
     p.block = default_block(L, P.nt, p.overlap, r);
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
@@ -612,6 +612,9 @@ struct Ctx {
     // contraction before block i + 2 starts overwriting its ring slots)
     hipStream_t aux = nullptr;
     hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_done[2] = {nullptr, nullptr};
+    // allocation-free call: tables uploaded from pageable memory (the call
+    // waits for that copy), contractions never overlapped
+    bool no_alloc = false;
 
     Ctx() = default;
     Ctx(const Ctx &) = delete;
@@ -751,7 +754,7 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     Tables T;
     st = build_tables(C.P, g, geo, &T);
     if (st != TPX_OK) return st;
-    C.plan = make_plan(C.P, mode, pr, T.blob.bytes.size());
+    C.plan = make_plan(C.P, mode, pr, T.blob.bytes.size(), !C.no_alloc);
     if (!ws || ws_bytes < C.plan.total) {
         char buf[160];
         snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes,
@@ -761,7 +764,16 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     C.ws = (unsigned char *)ws;
     C.stream = (hipStream_t)stream;
     unsigned char *tb = C.ws + C.plan.tables;
-    if (!T.blob.bytes.empty()) TPX_HIP(upload_async(tb, T.blob.bytes.data(), T.blob.bytes.size(), C.stream));
+    if (!T.blob.bytes.empty()) {
+        if (C.no_alloc) {
+            // no pinned staging: copy from the tables' own (pageable) memory and
+            // wait for the copy before that memory is released
+            TPX_HIP(hipMemcpyAsync(tb, T.blob.bytes.data(), T.blob.bytes.size(), hipMemcpyHostToDevice, C.stream));
+            TPX_HIP(hipStreamSynchronize(C.stream));
+        } else {
+            TPX_HIP(upload_async(tb, T.blob.bytes.data(), T.blob.bytes.size(), C.stream));
+        }
+    }
     C.src_inj = dev_inject(tb, T.src_inj);
     C.rec_inj = dev_inject(tb, T.rec_inj);
     C.rec_smp = dev_sample(tb, T.rec_smp);
@@ -1163,9 +1175,10 @@ struct GradJob {
 
 tpx_status job_init(GradJob &J, const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe, const float *m,
                     const float *d_obs, float *g, double *Jout, float *d_out, void *ws, size_t ws_bytes,
-                    void *stream) {
+                    void *stream, bool no_alloc = false) {
     if ((!d_obs && geom && geom->nrec > 0) || !g || !Jout)
         return fail(TPX_E_INVAL, "d_obs, g and J must not be NULL");
+    J.C.no_alloc = no_alloc;
     tpx_status st = setup(J.C, grid, geom, probe, M_GRAD_PROBED, m, ws, ws_bytes, stream);
     if (st != TPX_OK) return st;
     J.probe = *probe;
@@ -1242,6 +1255,38 @@ tpx_status guarded(F &&f) {
 }
 
 }  // namespace
+
+namespace tpx {
+
+void set_error(tpx_status st, const char *msg) { (void)fail(st, msg); }
+
+tpx_status gradient_probed_in_scratch(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe,
+                                      const float *m, const float *d_obs, float *g, double *J, float *d_out,
+                                      void *scratch, size_t scratch_bytes, void *stream) {
+    return guarded([&]() -> tpx_status {
+        // the size check first, with a message that names the limit
+        Problem P;
+        tpx_status st = make_problem(grid, geom, &P);
+        if (st != TPX_OK) return st;
+        if ((st = check_probe(P, probe)) != TPX_OK) return st;
+        Tables T;
+        if ((st = build_tables(P, grid, geom, &T)) != TPX_OK) return st;
+        const size_t need = make_plan(P, M_GRAD_PROBED, probe, T.blob.bytes.size(), false).total;
+        if (need > scratch_bytes) {
+            char buf[200];
+            snprintf(buf, sizeof buf,
+                     "the problem needs %zu bytes of scratch; the allocation-free entry point holds %zu bytes per GPU",
+                     need, scratch_bytes);
+            return fail(TPX_E_NOMEM, buf);
+        }
+        GradJob job;
+        st = job_init(job, grid, geom, probe, m, d_obs, g, J, d_out, scratch, scratch_bytes, stream, true);
+        if (st != TPX_OK) return st;
+        return job_advance(job, INT64_MAX);
+    });
+}
+
+}  // namespace tpx
 
 extern "C" {
 

@@ -7,6 +7,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "tpx.h"
+
 namespace tpx {
 
 // ---------------------------------------------------------------------------
@@ -193,5 +195,16 @@ hipError_t launch_range_finder(int S, int nt, int nrec, int r, const float *d_ob
 hipError_t launch_residual(const float *d, const float *dobs, float *res, int64_t n, double *partials,
                            int nparts, double *J, hipStream_t stream);
 int residual_parts(int64_t n);
+
+// Host runtime (runtime.cpp).  The probed gradient of tpx_gradient_probed run
+// in `scratch` (scratch_bytes long) without any allocation by the library:
+// geometry tables are copied from pageable host memory (the call waits for
+// that copy), contractions run in stream order.  Returns TPX_E_NOMEM, with a
+// message, when the problem needs more than scratch_bytes.
+tpx_status gradient_probed_in_scratch(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe,
+                                      const float *m, const float *d_obs, float *g, double *J, float *d_out,
+                                      void *scratch, size_t scratch_bytes, void *stream);
+// Record `msg` as the calling thread's tpx_last_error.
+void set_error(tpx_status st, const char *msg);
 
 }  // namespace tpx

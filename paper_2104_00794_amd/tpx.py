@@ -84,6 +84,7 @@ def lib():
     L.tpx_objective.argtypes = [P(_Grid), P(_Geom), vp, vp, vp, vp, vp, sz, vp]
     L.tpx_gradient_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, vp, vp, vp, sz, vp]
     L.tpx_gradient_full.argtypes = [P(_Grid), P(_Geom), vp, vp, vp, vp, vp, vp, sz, vp]
+    L.tpx_gradient_probed_noalloc.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, vp, vp, vp]
     L.tpx_forward_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp, sz, vp]
     L.tpx_backward_probed.argtypes = [P(_Grid), P(_Geom), P(_Probe), vp, vp, vp, sz, vp, vp, sz, vp]
     L.tpx_probe_matrix.argtypes = [P(_Probe), i32, i32, vp, vp]
@@ -103,6 +104,7 @@ def lib():
     L.tpx_profile_enable.restype = None
     L.tpx_profile_read.argtypes = [i32, P(ctypes.c_double), P(ctypes.c_int64)]
     for name in ("tpx_forward", "tpx_objective", "tpx_adjoint", "tpx_gradient_probed", "tpx_gradient_full",
+                 "tpx_gradient_probed_noalloc",
                  "tpx_forward_probed", "tpx_backward_probed", "tpx_probe_matrix", "tpx_check_workspace", "tpx_profile_read",
                  "tpx_job_create", "tpx_job_advance", "tpx_job_progress"):
         getattr(L, name).restype = ctypes.c_int
@@ -323,6 +325,29 @@ def gradient_probed(grid: Grid, geom: Geometry, probe: Probe, m, d_obs, ws=None,
                                      d.data_ptr() if d is not None else None, ws.data_ptr(), ws.numel(),
                                      _stream(stream)))
     return (g, J, d) if return_traces else (g, J)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def gradient_probed_noalloc(grid: Grid, geom: Geometry, probe: Probe, m, d_obs, g_out, J_out, stream=None,
+                            d_out=None):
+    """The probed gradient through the allocation-free entry point: the
+    library's static per-GPU scratch is the workspace, and the caller passes
+    every output (g_out, J_out, optionally d_out)."""
+    _dev_f32(m, grid.shape, "m")
+    _dev_f32(d_obs, (geom.nshots, grid.nt, geom.nrec), "d_obs")
+    _dev_f32(g_out, grid.shape, "g_out")
+    torch = _torch()
+    if not (isinstance(J_out, torch.Tensor) and J_out.is_cuda and J_out.dtype == torch.float64 and J_out.numel() >= 1):
+        raise TypeError("J_out must be a float64 CUDA tensor with at least one element")
+    if d_out is not None:
+        _dev_f32(d_out, (geom.nshots, grid.nt, geom.nrec), "d_out")
+    gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _check(lib().tpx_gradient_probed_noalloc(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
+                                             d_obs.data_ptr(), g_out.data_ptr(), J_out.data_ptr(),
+                                             d_out.data_ptr() if d_out is not None else None, _stream(stream)))
+    return g_out, J_out
 
 
 def gradient_full(grid: Grid, geom: Geometry, m, d_obs, ws=None, stream=None, return_traces: bool = False):
