@@ -157,7 +157,8 @@ enum {
 size_t tpx_workspace_bytes(int32_t call, const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe);
 
 /* Bytes of the state that tpx_forward_probed hands to tpx_backward_probed:
- * the probed forward wavefield ubar, S x r x N_phys floats. */
+ * the probed forward wavefield ubar, S x r x N_phys floats, followed by a
+ * 256-byte header naming the problem and probe set it was computed for. */
 size_t tpx_state_bytes(const tpx_grid *grid, const tpx_geom *geom, const tpx_probe *probe);
 
 /* Forward modelling F(m; q), Eq. (2):  d[S][nt][nrec] (device). */
@@ -268,7 +269,11 @@ int64_t tpx_get_option(int32_t option);
 
 /* Device-side checks of the last call that used `ws`, after waiting for
  * `stream`: TPX_E_NUMERIC if the model held a non-finite or non-positive
- * value, TPX_E_CFL if it held a velocity above damp_vmax. */
+ * value, TPX_E_CFL if it held a velocity above damp_vmax, TPX_E_STATE if
+ * tpx_backward_probed was given a state that a forward pass of another
+ * problem or probe set (kind, r, seed, side, explicit Z, grid, shots, nt)
+ * wrote.  The backward pass itself runs regardless; its result is then
+ * meaningless. */
 tpx_status tpx_check_workspace(const void *ws, void *stream);
 
 /* Kernel timing for measurement: while enabled, each run of consecutive

@@ -984,6 +984,24 @@ hipError_t launch_model_prep(const Layout &L, const float *m, double dt, float m
     return hipGetLastError();
 }
 
+// Header of a probed forward pass's state: the problem and probes it belongs
+// to, written by the forward pass and compared by the backward pass, which
+// sets flags bit 2 on a mismatch.
+__global__ __launch_bounds__(64) void k_state_header(StateHeader h, int32_t *hdr, int32_t *flags, int check) {
+    const int i = threadIdx.x;
+    if (i >= StateHeader::kWords) return;
+    if (!check) {
+        hdr[i] = h.w[i];
+    } else if (hdr[i] != h.w[i]) {
+        atomicOr(flags, 4);
+    }
+}
+
+hipError_t launch_state_header(const StateHeader &h, void *hdr, int32_t *flags, int check, hipStream_t stream) {
+    hipLaunchKernelGGL(k_state_header, dim3(1), dim3(64), 0, stream, h, (int32_t *)hdr, flags, check);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero(float4 *p, int64_t n4) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += (int64_t)gridDim.x * 256)
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);

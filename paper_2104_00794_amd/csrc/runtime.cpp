@@ -1256,6 +1256,39 @@ tpx_status guarded(F &&f) {
 
 }  // namespace
 
+namespace {
+
+// ubar occupies the start of a state buffer; the header follows it.
+size_t state_ubar_bytes(const Problem &P, const tpx_probe *pr) { return align_up((size_t)P.L.S * pr->r * P.L.nphys * 4); }
+size_t state_total_bytes(const Problem &P, const tpx_probe *pr) {
+    return state_ubar_bytes(P, pr) + align_up(sizeof(StateHeader));
+}
+
+StateHeader state_header(const Problem &P, const tpx_probe *pr) {
+    StateHeader h;
+    memset(&h, 0, sizeof h);
+    h.w[0] = 0x31585054;   // "TPX1"
+    h.w[1] = (int32_t)pr->kind;
+    h.w[2] = pr->r;
+    h.w[3] = (int32_t)(pr->seed & 0xffffffffu);
+    h.w[4] = (int32_t)(pr->seed >> 32);
+    h.w[5] = pr->dtt_side;
+    h.w[6] = P.nt;
+    h.w[7] = P.L.S;
+    h.w[8] = (int32_t)P.L.n[0];
+    h.w[9] = (int32_t)P.L.n[1];
+    h.w[10] = (int32_t)P.L.n[2];
+    h.w[11] = P.L.R;
+    h.w[12] = P.L.nb;
+    const uint64_t z = (uint64_t)(uintptr_t)pr->Z;   // explicit probes: the same matrix
+    h.w[13] = (int32_t)(z & 0xffffffffu);
+    h.w[14] = (int32_t)(z >> 32);
+    h.w[15] = (int32_t)(pr->scale * 1e6);
+    return h;
+}
+
+}  // namespace
+
 namespace tpx {
 
 void set_error(tpx_status st, const char *msg) { (void)fail(st, msg); }
@@ -1323,7 +1356,7 @@ size_t tpx_state_bytes(const tpx_grid *grid, const tpx_geom *geom, const tpx_pro
         tpx_status st = make_problem(grid, geom, &P);
         if (st != TPX_OK) return st;
         if ((st = check_probe(P, probe)) != TPX_OK) return st;
-        out = align_up((size_t)P.L.S * probe->r * P.L.nphys * 4);
+        out = state_total_bytes(P, probe);
         return TPX_OK;
     });
     return out;
@@ -1458,11 +1491,17 @@ tpx_status tpx_forward_probed(const tpx_grid *grid, const tpx_geom *geom, const 
         Ctx C;
         tpx_status st = setup(C, grid, geom, probe, M_FWD_PROBED, m, ws, ws_bytes, stream);
         if (st != TPX_OK) return st;
-        const size_t need = align_up((size_t)C.P.L.S * probe->r * C.P.L.nphys * 4);
-        if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
+        if (state_bytes < state_total_bytes(C.P, probe))
+            return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
         const float *Z = probe_matrix_dev(C, probe, nullptr, &st);
         if (st != TPX_OK) return st;
-        return run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, (float *)state, probe->dtt_side);
+        st = run_forward(C, geom->wavelet, d, nullptr, Z, probe->r, (float *)state, probe->dtt_side);
+        if (st != TPX_OK) return st;
+        TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
+            return launch_state_header(state_header(C.P, probe), (unsigned char *)state + state_ubar_bytes(C.P, probe),
+                                       (int32_t *)(C.ws + C.plan.flags), 0, C.stream);
+        }));
+        return TPX_OK;
     });
 }
 
@@ -1475,8 +1514,14 @@ tpx_status tpx_backward_probed(const tpx_grid *grid, const tpx_geom *geom, const
         tpx_status st = setup(C, grid, geom, probe, M_BWD_PROBED, m, ws, ws_bytes, stream);
         if (st != TPX_OK) return st;
         const Layout &L = C.P.L;
-        const size_t need = align_up((size_t)L.S * probe->r * L.nphys * 4);
-        if (state_bytes < need) return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
+        if (state_bytes < state_total_bytes(C.P, probe))
+            return fail(TPX_E_STATE, "state buffer smaller than tpx_state_bytes()");
+        // the state must come from a forward pass of this problem and probe set
+        TPX_HIP(prof(KIND_OTHER, C.stream, [&] {
+            return launch_state_header(state_header(C.P, probe),
+                                       (unsigned char *)const_cast<void *>(state) + state_ubar_bytes(C.P, probe),
+                                       (int32_t *)(C.ws + C.plan.flags), 1, C.stream);
+        }));
         const float *Z = probe_matrix_dev(C, probe, nullptr, &st);
         if (st != TPX_OK) return st;
         AdjOut o;
@@ -1563,6 +1608,8 @@ tpx_status tpx_check_workspace(const void *ws, void *stream) {
         TPX_HIP(hipMemcpy(&flags, ws, sizeof flags, hipMemcpyDeviceToHost));
         if (flags & 1) return fail(TPX_E_NUMERIC, "the model holds a non-finite or non-positive value");
         if (flags & 2) return fail(TPX_E_CFL, "the model holds velocities above damp_vmax (dt may be unstable)");
+        if (flags & 4)
+            return fail(TPX_E_STATE, "the state was written by a forward pass of another problem or probe set");
         return TPX_OK;
     });
 }

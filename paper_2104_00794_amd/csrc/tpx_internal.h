@@ -145,6 +145,14 @@ hipError_t launch_sample_only(const Layout &L, const float *field, int k, const 
 hipError_t launch_model_prep(const Layout &L, const float *m, double dt, float m_min, float *beta, int32_t *flags,
                              hipStream_t stream);
 hipError_t launch_fill_zero(void *ptr, size_t bytes, hipStream_t stream);
+// Identity of a probed forward pass (problem sizes and probe set), kept after
+// ubar in its state buffer.
+struct StateHeader {
+    static constexpr int kWords = 16;
+    int32_t w[kWords];
+};
+// check == 0: write h into hdr; check == 1: set flags bit 2 where hdr differs from h.
+hipError_t launch_state_header(const StateHeader &h, void *hdr, int32_t *flags, int check, hipStream_t stream);
 hipError_t launch_probe_gen(int kind, int r, uint64_t seed, int nt, int shot0, int nshots, float *Z,
                             hipStream_t stream);
 hipError_t launch_probe_copy(const float *Zsrc, int64_t n, float *Zdst, hipStream_t stream);

@@ -171,6 +171,8 @@ class Server:
                 waiting.remove(req)
                 nlarge += 1 if self._large(req) else 0
                 stream = free_streams.pop()
+                # the job's inputs (m, d_obs) come from the caller's stream
+                stream.wait_stream(torch.cuda.current_stream(self.device))
                 with torch.cuda.stream(stream):
                     ws = torch.empty(wsb[req.rid], dtype=torch.uint8, device=self.device)
                     job = tpx.Job(req.grid, req.geom, req.probe, req.m, req.d_obs, ws=ws, stream=stream)

@@ -222,6 +222,21 @@ def _stream(stream=None) -> int:
     return s.cuda_stream
 
 
+def _use_on(stream, *tensors):
+    """The library reads and writes `tensors` on `stream`.  When that is not
+    the current stream (on which PyTorch's caching allocator may have placed
+    them), mark them in use there, so their memory is not handed to another
+    allocation before `stream` has finished with it."""
+    if stream is None:
+        return
+    torch = _torch()
+    if stream == torch.cuda.current_stream(stream.device):
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 def _dev_f32(t, shape=None, name="tensor"):
     torch = _torch()
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
@@ -275,6 +290,7 @@ def forward(grid: Grid, geom: Geometry, m, ws=None, stream=None):
     d = torch.empty((geom.nshots, grid.nt, geom.nrec), dtype=torch.float32, device=m.device)
     ws = _ws(ws, CALL_FORWARD, grid, geom, None, m.device)
     g, ge = grid.c(), geom.c()
+    _use_on(stream, m, d, ws)
     _check(lib().tpx_forward(ctypes.byref(g), ctypes.byref(ge), m.data_ptr(), d.data_ptr(), ws.data_ptr(),
                              ws.numel(), _stream(stream)))
     return d
@@ -290,6 +306,7 @@ def objective(grid: Grid, geom: Geometry, m, d_obs, ws=None, stream=None, J_out=
         else None
     ws = _ws(ws, CALL_OBJECTIVE, grid, geom, None, m.device)
     g, ge = grid.c(), geom.c()
+    _use_on(stream, m, d_obs, J, d, ws)
     _check(lib().tpx_objective(ctypes.byref(g), ctypes.byref(ge), m.data_ptr(), d_obs.data_ptr(), J.data_ptr(),
                                d.data_ptr() if d is not None else None, ws.data_ptr(), ws.numel(), _stream(stream)))
     return (J, d) if return_traces else J
@@ -303,6 +320,7 @@ def adjoint(grid: Grid, geom: Geometry, m, d_in, ws=None, stream=None):
     q = torch.empty((geom.nshots, grid.nt), dtype=torch.float32, device=m.device)
     ws = _ws(ws, CALL_ADJOINT, grid, geom, None, m.device)
     g, ge = grid.c(), geom.c()
+    _use_on(stream, m, d_in, q, ws)
     _check(lib().tpx_adjoint(ctypes.byref(g), ctypes.byref(ge), m.data_ptr(), d_in.data_ptr(), q.data_ptr(),
                              ws.data_ptr(), ws.numel(), _stream(stream)))
     return q
@@ -320,6 +338,7 @@ def gradient_probed(grid: Grid, geom: Geometry, probe: Probe, m, d_obs, ws=None,
         else None
     ws = _ws(ws, CALL_GRADIENT_PROBED, grid, geom, probe, m.device)
     gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _use_on(stream, m, d_obs, g, J, d, ws, probe.Z)
     _check(lib().tpx_gradient_probed(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
                                      d_obs.data_ptr(), g.data_ptr(), J.data_ptr(),
                                      d.data_ptr() if d is not None else None, ws.data_ptr(), ws.numel(),
@@ -344,6 +363,7 @@ def gradient_probed_noalloc(grid: Grid, geom: Geometry, probe: Probe, m, d_obs, 
     if d_out is not None:
         _dev_f32(d_out, (geom.nshots, grid.nt, geom.nrec), "d_out")
     gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _use_on(stream, m, d_obs, g_out, J_out, d_out, probe.Z)
     _check(lib().tpx_gradient_probed_noalloc(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
                                              d_obs.data_ptr(), g_out.data_ptr(), J_out.data_ptr(),
                                              d_out.data_ptr() if d_out is not None else None, _stream(stream)))
@@ -361,6 +381,7 @@ def gradient_full(grid: Grid, geom: Geometry, m, d_obs, ws=None, stream=None, re
         else None
     ws = _ws(ws, CALL_GRADIENT_FULL, grid, geom, None, m.device)
     gc, ge = grid.c(), geom.c()
+    _use_on(stream, m, d_obs, g, J, d, ws)
     _check(lib().tpx_gradient_full(ctypes.byref(gc), ctypes.byref(ge), m.data_ptr(), d_obs.data_ptr(),
                                    g.data_ptr(), J.data_ptr(), d.data_ptr() if d is not None else None,
                                    ws.data_ptr(), ws.numel(), _stream(stream)))
@@ -376,6 +397,7 @@ def forward_probed(grid: Grid, geom: Geometry, probe: Probe, m, ws=None, state=N
         state = torch.empty(state_bytes(grid, geom, probe), dtype=torch.uint8, device=m.device)
     ws = _ws(ws, CALL_FORWARD_PROBED, grid, geom, probe, m.device)
     gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _use_on(stream, m, d, state, ws, probe.Z)
     _check(lib().tpx_forward_probed(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
                                     d.data_ptr(), state.data_ptr(), state.numel(), ws.data_ptr(), ws.numel(),
                                     _stream(stream)))
@@ -390,6 +412,7 @@ def backward_probed(grid: Grid, geom: Geometry, probe: Probe, m, grad_d, state, 
     g = torch.empty(tuple(grid.shape), dtype=torch.float32, device=m.device)
     ws = _ws(ws, CALL_BACKWARD_PROBED, grid, geom, probe, m.device)
     gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _use_on(stream, m, grad_d, state, g, ws, probe.Z)
     _check(lib().tpx_backward_probed(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
                                      grad_d.data_ptr(), state.data_ptr(), state.numel(), g.data_ptr(),
                                      ws.data_ptr(), ws.numel(), _stream(stream)))
@@ -404,6 +427,7 @@ def range_finder_probes(grid: Grid, geom: Geometry, probe: Probe, d_obs, ws=None
     Q = torch.empty((geom.nshots, grid.nt, probe.r), dtype=torch.float32, device=d_obs.device)
     ws = _ws(ws, CALL_RANGE_FINDER, grid, geom, probe, d_obs.device)
     gc, ge, pc = grid.c(), geom.c(), probe.c()
+    _use_on(stream, d_obs, Q, ws)
     _check(lib().tpx_range_finder_probes(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), d_obs.data_ptr(),
                                          Q.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
     return Q
@@ -414,6 +438,7 @@ def probe_matrix(probe: Probe, nt: int, shot: int, device=None, stream=None):
     torch = _torch()
     Z = torch.empty((nt, probe.r), dtype=torch.float32, device=device or "cuda")
     pc = probe.c()
+    _use_on(stream, Z)
     _check(lib().tpx_probe_matrix(ctypes.byref(pc), int(nt), int(shot), Z.data_ptr(), _stream(stream)))
     return Z
 
@@ -435,6 +460,7 @@ class Job:
         self.ws = _ws(ws, CALL_GRADIENT_PROBED, grid, geom, probe, m.device)
         gc, ge, pc = grid.c(), geom.c(), probe.c()
         h = ctypes.c_void_p()
+        _use_on(stream, m, d_obs, self.g, self.J, self.ws, probe.Z)
         _check(lib().tpx_job_create(ctypes.byref(gc), ctypes.byref(ge), ctypes.byref(pc), m.data_ptr(),
                                     d_obs.data_ptr(), self.g.data_ptr(), self.J.data_ptr(), None,
                                     self.ws.data_ptr(), self.ws.numel(), _stream(stream), ctypes.byref(h)))
@@ -444,6 +470,7 @@ class Job:
     def advance(self, max_steps: int, stream=None) -> bool:
         """Enqueue up to max_steps time steps; True once all work is enqueued."""
         fin = ctypes.c_int32(0)
+        _use_on(stream, self.m, self.d_obs, self.g, self.J, self.ws, self.probe.Z)
         _check(lib().tpx_job_advance(self._h, int(max_steps), _stream(stream), ctypes.byref(fin)))
         self.finished = bool(fin.value)
         return self.finished

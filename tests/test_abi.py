@@ -162,7 +162,8 @@ def test_memory_follows_the_papers_estimates():
         return (b + 255) // 256 * 256
 
     for r in (4, 8, 16):
-        assert tpx.state_bytes(grid, geom, tpx.Probe(r=r)) == a(S * r * N * 4)
+        # u-bar, then a 256-byte header naming the forward pass that wrote it
+        assert tpx.state_bytes(grid, geom, tpx.Probe(r=r)) == a(S * r * N * 4) + 256
         keep = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=r, keep_vbar=True))
         fold = tpx.workspace_bytes(tpx.CALL_GRADIENT_PROBED, grid, geom, tpx.Probe(r=r))
         # v-bar replaces the folded path's one-field partial gradient
