@@ -290,6 +290,28 @@ def test_split_forward_backward_equals_gradient_call():
     assert np.array_equal(to_np(g1), to_np(g2))
 
 
+def test_backward_reports_a_state_from_another_probe_set():
+    # the state carries the identity of the forward pass that wrote it; the
+    # backward pass compares it on the device and tpx_check_workspace reports
+    # a mismatch (other seed, other r with the same state size, other side)
+    import torch
+    c = Case(small_2d(nz=30, nx=60, nt=100, nshots=2, nrec=9))
+    dobs = c.dobs_oracle()
+    m, d = cuda(c.m0), cuda(dobs)
+    p5 = tpx.Probe(r=8, seed=5)
+    dsp, state = tpx.forward_probed(c.tgrid(), c.tgeom(), p5, m)
+    ws = tpx.alloc_workspace(tpx.CALL_BACKWARD_PROBED, c.tgrid(), c.tgeom(), p5)
+    tpx.backward_probed(c.tgrid(), c.tgeom(), p5, m, dsp - d, state, ws=ws)
+    tpx.check_workspace(ws)
+    for other in (tpx.Probe(r=8, seed=6), tpx.Probe(r=8, seed=5, dtt_side=1), tpx.Probe(r=8, seed=5, kind="gauss_b64")):
+        ws2 = tpx.alloc_workspace(tpx.CALL_BACKWARD_PROBED, c.tgrid(), c.tgeom(), other)
+        tpx.backward_probed(c.tgrid(), c.tgeom(), other, m, dsp - d, state, ws=ws2)
+        with pytest.raises(tpx.TpxError) as e:
+            tpx.check_workspace(ws2)
+        assert e.value.status == tpx.E_STATE
+    torch.cuda.synchronize()
+
+
 def test_concurrent_host_threads():
     # four host threads, each with its own stream, problem and workspace, call
     # the library at once (ctypes releases the GIL); every result equals the
@@ -443,33 +465,62 @@ def test_c1_full_configuration():
     assert abs(float(J_g.item()) - J_o) <= TOL * J_o
 
 
-def test_c3_full_grid_truncated_record():
+# source positions (x, y, z in metres) on the 401 x 401 x 301 grid at 12.5 m:
+# near the top face; at mid depth next to the x = max and y = 0 faces; at the
+# bottom next to the x = 0, y = max and z = max faces.  Each one's 40-step
+# record reaches the absorbing layer of its faces and spans two or three z
+# chunks of both step kernels, so the three together cover all six faces and
+# the first, middle and last chunks.
+C3_SOURCES = [(2500.0, 2500.0, 50.0), (4930.0, 70.0, 1880.0), (60.0, 4940.0, 3690.0)]
+
+
+@pytest.mark.parametrize("src", C3_SOURCES)
+def test_c3_full_grid_truncated_record(src):
     # 401 x 401 x 301 at 12.5 m (the 3D configuration's grid and launch shape),
-    # 40,401 receivers, r = 32; record truncated to 40 steps (30 Hz wavelet)
-    # so the FP64 oracle finishes in about a minute; the gradient is compared
-    # at 4096 sampled points computed by the oracle one by one.
-    _print_case("c3_truncated")
+    # r = 32; record truncated to 40 steps (30 Hz wavelet) so the FP64 oracle
+    # finishes in about a minute; receivers around the source; the gradient is
+    # compared at 4096 points around the source computed by the oracle one by
+    # one, for one-step and for fused two-step 3D launches.
+    import torch
+    _print_case("c3_truncated", src=src)
     wl = workload("c3_layered_3d").with_(nt=40, f_khz=0.03)
+    h = wl.h
+    nz, ny, nx = wl.shape
+    ext = [(nx - 1) * h, (ny - 1) * h, (nz - 1) * h]
+    rec = [tuple(min(max(src[a] + off[a], 0.0), ext[a]) for a in range(3))
+           for off in [(dx * 2.3 * h, dy * 2.1 * h, dz * 1.9 * h) for dx in (-2, 0, 2) for dy in (-2, 0, 2)
+                       for dz in (-1, 1)]]
+    wl = wl.with_(src=[src], rec=rec)
     c = Case(wl)
-    d_g = tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true))
     d_o = oracle.forward(c.ogrid(), c.m_true, c.src, c.rec, c.wav)
-    assert rel_l2(to_np(d_g), d_o) <= TOL
     dobs = np.zeros_like(d_o)
     rng = np.random.default_rng(0)
-    # sample points near the source where the wavefield is non-zero after 70 steps
-    nz, ny, nx = wl.shape
-    zz = rng.integers(0, 12, 4096)
-    yy = rng.integers(190, 211, 4096)
-    xx = rng.integers(190, 211, 4096)
+    ci = [int(round(src[a] / h)) for a in range(3)]   # x, y, z indices of the source
+    lo = [max(ci[a] - 12, 0) for a in range(3)]
+    hi = [min(ci[a] + 13, (nx, ny, nz)[a]) for a in range(3)]
+    xx, yy, zz = (rng.integers(lo[a], hi[a], 4096) for a in range(3))
     pts = (zz * ny + yy) * nx + xx
     g_o, J_o = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=wl.r, seed=wl.probe_seed,
                                       points=pts)
-    g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=wl.r, seed=wl.probe_seed), cuda(c.m0),
-                                   cuda(dobs))
-    g_s = to_np(g_g).reshape(-1)[pts]
     assert np.linalg.norm(g_o) > 0
-    assert rel_l2(g_s, g_o) <= TOL
-    assert abs(float(J_g.item()) - J_o) <= TOL * J_o
+    print("[c3] points on faces (x, y, z):",
+          [int(np.sum(v == 0)) + int(np.sum(v == n - 1)) for v, n in ((xx, nx), (yy, ny), (zz, nz))], flush=True)
+    for fused in (0, 1):
+        try:
+            tpx.set_option(tpx.OPT_FUSED_STEPS_3D, fused)
+            d_g = tpx.forward(c.tgrid(), c.tgeom(), cuda(c.m_true))
+            g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=wl.r, seed=wl.probe_seed), cuda(c.m0),
+                                           cuda(dobs))
+            torch.cuda.synchronize()
+        finally:
+            tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 0)
+        g_s = g_g.reshape(-1).index_select(0, torch.as_tensor(pts, device="cuda")).double().cpu().numpy()
+        del g_g
+        print("[c3] fused", fused, "traces rel", rel_l2(to_np(d_g), d_o), "gradient rel", rel_l2(g_s, g_o),
+              flush=True)
+        assert rel_l2(to_np(d_g), d_o) <= TOL
+        assert rel_l2(g_s, g_o) <= TOL
+        assert abs(float(J_g.item()) - J_o) <= TOL * J_o
 
 
 def test_largest_2d_shot_fields():

@@ -53,15 +53,21 @@ def test_taylor_second_order(ndim):
     assert J0 == pytest.approx(_J(grid, wl, m0, dobs), rel=1e-12)
     dm = _edge_free(mt - m0)
     gdm = float(np.sum(g * dm))
+    # h = 0.1 ... 9.8e-5, halving: in FP64 the first-order remainder halves and
+    # the second-order one quarters all the way down (ratios 2.000 and 4.000
+    # from h = 2.5e-2 on; the smallest second-order remainder is ~1e-8 J0)
+    hs = [0.1 / 2 ** i for i in range(11)]
     r1, r2 = [], []
-    for h in (0.1, 0.05, 0.025, 0.0125):
+    for h in hs:
         Jh = _J(grid, wl, m0 + h * dm, dobs)
         r1.append(abs(Jh - J0))
         r2.append(abs(Jh - J0 - h * gdm))
-    q1 = [r1[i] / r1[i + 1] for i in range(3)]
-    q2 = [r2[i] / r2[i + 1] for i in range(3)]
-    assert all(1.8 < q < 2.2 for q in q1), q1
-    assert all(3.6 < q < 4.4 for q in q2), q2
+    q1 = [r1[i] / r1[i + 1] for i in range(len(hs) - 1)]
+    q2 = [r2[i] / r2[i + 1] for i in range(len(hs) - 1)]
+    assert hs[-1] < 1e-4
+    assert all(1.9 < q < 2.1 for q in q1), q1
+    assert all(3.9 < q < 4.1 for q in q2), q2
+    assert all(abs(q - 4.0) < 0.01 for q in q2[3:]), q2
 
 
 @pytest.mark.parametrize("order", [4, 8])

@@ -113,3 +113,17 @@ def test_absorbing_layer_removes_boundary_reflection():
     refl_rigid = np.sum((rigid - ref) ** 2) / e_ref
     assert refl_rigid > 0.1
     assert refl_damped < 0.02 * refl_rigid
+
+
+def test_damping_strength_gives_round_trip_amplitude_sqrt_R():
+    # A plane wave in m u_tt + m d u_t = Lap u decays as exp(-d x / (2 v)) when
+    # d << omega, so a round trip through the layer (d = dmax (x/L)^2) keeps
+    # exp(-dmax L / (3 v)) of its amplitude: sqrt(R) for dmax = 3 v ln(1/R) / (2 L).
+    # While damping is weak the reflection off the layer is that round trip,
+    # so its amplitude scales as R^(1/2); a dmax off by a factor 2 gives R or R^(1/4).
+    ref = _homogeneous_trace(301, 0, 1.0)
+    rigid = np.sqrt(np.sum((_homogeneous_trace(41, 20, 1.0) - ref) ** 2))
+    amp = {R: np.sqrt(np.sum((_homogeneous_trace(41, 20, R) - ref) ** 2)) / rigid for R in (0.3, 0.1, 0.01)}
+    for lo, hi in ((0.1, 0.3), (0.01, 0.1)):
+        slope = np.log(amp[hi] / amp[lo]) / np.log(hi / lo)
+        assert 0.4 < slope < 0.6, (lo, hi, slope)
