@@ -121,9 +121,19 @@ __device__ __forceinline__ void buf_store(float v, __amdgpu_buffer_rsrc_t r, uin
 // mod 8, so logical tile (b mod 8) * (nblocks / 8) + b / 8 gives every XCD a
 // contiguous run of tiles whose halos then hit in that XCD's L2.
 // ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) const float lds_f32;
+// An LDS row address the compiler cannot fold into another row's: the reads of
+// one row then pair up with small offsets from it, one address add per row
+// instead of one per pair of reads.
+__device__ __forceinline__ const lds_f32 *lds_row(const float *p) {
+    const lds_f32 *q = (const lds_f32 *)p;
+    asm volatile("" : "+v"(q));
+    return q;
+}
+
 template <int R, int NSTEP, bool FAST, int TZ>
 __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot, int tile,
-                                            int x0, int z0, float (*U)[64 + 2 * R], float (*V)[64]) {
+                                            int x0, int z0, float (*U)[64 + 2 * R], float (*V)[64 + 2 * R]) {
 #pragma clang fp contract(off)
     constexpr int TX = t2x(R);
     constexpr int SH = TZ + 4 * R;            // staged rows of u^k
@@ -236,10 +246,10 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
             const int z = zb + q, ur = w * NQ + q + 2 * R;
             const float cv = col[q + R];
             float lap = 2.0f * ph.c[0] * cv;
+            const lds_f32 *up = lds_row(&U[ur][lx]);
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap = __builtin_fmaf(ph.c[k], (U[ur][lx + R - k] + U[ur][lx + R + k]) + (col[q + R - k] + col[q + R + k]),
-                                     lap);
+                lap = __builtin_fmaf(ph.c[k], (up[R - k] + up[R + k]) + (col[q + R - k] + col[q + R + k]), lap);
             float v;
             if (FAST) {
                 v = leapfrog0(cv, p[q], b[q], lap, s1[q]);
@@ -250,7 +260,7 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
             if (NSTEP == 1) {
                 if (act && (FAST || z < P2)) buf_store(v, rn1, ox, rowoff(z));
             } else {
-                V[w * NQ + q + R][lx] = v;
+                V[w * NQ + q + R][lx + R] = v;
             }
             c[q] = cv;
         }
@@ -263,12 +273,12 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
         const int hr = w + 4 * i;
         const int z = hr < R ? z0 - R + hr : z0 + TZ + (hr - R);
         const int ur = z - z0 + 2 * R;
-        const float cv = U[ur][lx + R];
+        const lds_f32 *up = lds_row(&U[ur][lx]);
+        const float cv = up[R];
         float lap = 2.0f * ph.c[0] * cv;
 #pragma unroll
         for (int k = 1; k <= R; ++k)
-            lap = __builtin_fmaf(ph.c[k], (U[ur][lx + R - k] + U[ur][lx + R + k]) + (U[ur - k][lx + R] + U[ur + k][lx + R]),
-                                 lap);
+            lap = __builtin_fmaf(ph.c[k], (up[R - k] + up[R + k]) + (U[ur - k][lx + R] + U[ur + k][lx + R]), lap);
         float v;
         if (FAST) {
             v = leapfrog0(cv, hp[i], hb[i], lap, sh[i]);
@@ -276,7 +286,7 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
             const float h = ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb));
             v = (xin && z >= 0 && z < P2) ? leapfrog(cv, hp[i], hb[i], lap, sh[i], h) : 0.0f;
         }
-        V[hr < R ? hr : TZ + hr][lx] = v;
+        V[hr < R ? hr : TZ + hr][lx + R] = v;
     }
     __syncthreads();
 
@@ -284,17 +294,18 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
     const __amdgpu_buffer_rsrc_t rn2 = buf_rsrc(a.next2 + so, span);
     float col[NQ + 2 * R];
 #pragma unroll
-    for (int i = 0; i < NQ + 2 * R; ++i) col[i] = V[w * NQ + i][lx];
+    for (int i = 0; i < NQ + 2 * R; ++i) col[i] = V[w * NQ + i][lx + R];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int z = zb + q, vr = w * NQ + q + R;
         const float v = col[q + R];
         float lap = 2.0f * ph.c[0] * v;
+        // V's rows carry R spare columns on each side, so the idle edge lanes
+        // read inside the array (values they never store)
+        const lds_f32 *vp = lds_row(&V[vr][lx]);
 #pragma unroll
-        for (int k = 1; k <= R; ++k) {
-            const int xl = lx - k < 0 ? 0 : lx - k, xr = lx + k > 63 ? 63 : lx + k;   // in-range reads for idle lanes
-            lap = __builtin_fmaf(ph.c[k], (V[vr][xl] + V[vr][xr]) + (col[q + R - k] + col[q + R + k]), lap);
-        }
+        for (int k = 1; k <= R; ++k)
+            lap = __builtin_fmaf(ph.c[k], (vp[R - k] + vp[R + k]) + (col[q + R - k] + col[q + R + k]), lap);
         if (act && (FAST || z < P2)) {
             const uint32_t ro = rowoff(z);
             buf_store(v, rn1, ox, ro);
@@ -307,7 +318,7 @@ template <int R, int NSTEP, int TZ>
 __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph, const StepArgs a) {
     constexpr int TX = t2x(R);
     __shared__ float U[TZ + 4 * R][64 + 2 * R];
-    __shared__ float V[NSTEP == 2 ? TZ + 2 * R : 1][64];
+    __shared__ float V[NSTEP == 2 ? TZ + 2 * R : 1][64 + 2 * R];
     const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2], nsp = ntx * ntz;
     const int lid = xcd_logical_block(nsp * L.S);
     if (lid < 0) return;

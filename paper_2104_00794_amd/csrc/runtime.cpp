@@ -823,8 +823,11 @@ struct FwdLoop {
 
 // Two fused steps are used whenever both steps fall in the caller's budget
 // and in one contraction block (the ring holds one block plus the two levels
-// around it).  They are skipped when contractions overlap the steps.
-bool two_steps_allowed(const Ctx &C) { return !C.plan.overlap && (C.P.L.ndim == 2 || g_fused3d.load() != 0); }
+// around it).  With overlapped contractions too: a block's contraction reads
+// levels s_lo - 1 .. s_hi + 1 while the next block writes the b levels beyond
+// them, 2 b + 2 distinct levels in a ring of 2 b + 3 slots, however the steps
+// are paired.
+bool two_steps_allowed(const Ctx &C) { return C.P.L.ndim == 2 || g_fused3d.load() != 0; }
 
 tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
                      float *ubar, int dtt = 0) {

@@ -614,12 +614,15 @@ def test_largest_3d_shot_field():
     assert abs(float(J_g.item()) - J_o) <= TOL * J_o
 
 
-def test_overlapped_contractions_are_bitwise_identical():
+@pytest.mark.parametrize("block", [16, 15])
+def test_overlapped_contractions_are_bitwise_identical(block):
     # contractions on the auxiliary stream (ring of 2b + 3 slots) give the same
-    # bits as in stream order: same kernels, same summation order
+    # bits as in stream order: same kernels, same summation order, with fused
+    # two-step launches paired differently around odd block ends
+    _print_case("overlap_2d", block=block)
     c = Case(small_2d(nz=30, nx=90, nt=170, nshots=2, nrec=11))
     dobs = c.dobs_oracle()
-    probe = tpx.Probe(r=8, seed=4, block=16)
+    probe = tpx.Probe(r=8, seed=4, block=block)
     try:
         tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 0)
         a, Ja = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, cuda(c.m0), cuda(dobs))
@@ -658,11 +661,15 @@ def test_3d_split_job_and_overlap_are_bitwise_identical():
     try:
         tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 1)
         g_ovl, J_ovl = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d)
+        tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 1)
+        g_ovl2, J_ovl2 = tpx.gradient_probed(c.tgrid(), c.tgeom(), probe, m, d)
     finally:
         tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 0)
+        tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 0)
     torch.cuda.synchronize()
     assert torch.equal(g_split, g) and torch.equal(job.g, g) and torch.equal(job.J, J)
     assert torch.equal(g_ovl, g) and torch.equal(J_ovl, J)
+    assert torch.equal(g_ovl2, g) and torch.equal(J_ovl2, J)
     g_o, _ = oracle.gradient_probed(c.ogrid(), c.m0, c.src, c.rec, c.wav, dobs, r=32, seed=6)
     assert rel_l2(to_np(g), g_o) <= TOL
 
