@@ -74,6 +74,8 @@ def parse():
                     help="requests of the serving sub-record (0: skip)")
     ap.add_argument("--fused-3d", type=int, default=None, choices=[0, 1],
                     help="two leapfrog steps per 3D launch (library option; default: the library's)")
+    ap.add_argument("--steps-2d", type=int, default=None, choices=[2, 3],
+                    help="most leapfrog steps per 2D launch (default: the library's, 2)")
     return ap.parse_args()
 
 
@@ -126,6 +128,8 @@ def main():
         tpx.set_option(tpx.OPT_MATRIX_CORES, args.matrix_cores)
     if args.fused_3d is not None:
         tpx.set_option(tpx.OPT_FUSED_STEPS_3D, args.fused_3d)
+    if args.steps_2d is not None:
+        tpx.set_option(tpx.OPT_STEPS_2D, args.steps_2d)
     if args.serving:
         print(json.dumps(serving(args, dev)), flush=True)
         return
@@ -286,22 +290,23 @@ def gradient_record(args, wl, steps, warmup, dev, profile=True, default_probe=Fa
         tpx.profile_enable(True)
         step()
         torch.cuda.synchronize()
-        for name, kid in (("step2", tpx.KERNEL_STEP2), ("step", tpx.KERNEL_STEP),
+        for name, kid in (("step3", tpx.KERNEL_STEP3), ("step2", tpx.KERNEL_STEP2), ("step", tpx.KERNEL_STEP),
                           ("accum_fwd", tpx.KERNEL_ACCUM_FWD), ("accum_adj", tpx.KERNEL_ACCUM_ADJ),
                           ("accum_full", tpx.KERNEL_ACCUM_FULL)):
             tot, n = tpx.profile_read(kid)
             kernels[name] = {"total_ms": round(tot, 4), "launches": n,
                              "avg_us": round(1e3 * tot / n, 3) if n else None}
         tpx.profile_enable(False)
-        # dominant kernel: the step kernel with the larger total time
-        two = kernels["step2"]["total_ms"] >= kernels["step"]["total_ms"]
-        st = kernels["step2" if two else "step"]
-        nstep = 2 if two else 1
+        # dominant kernel: the step kernel kind with the largest total time
+        dom = max(("step3", "step2", "step"), key=lambda n: kernels[n]["total_ms"])
+        st = kernels[dom]
+        nstep = {"step3": 3, "step2": 2, "step": 1}[dom]
         R = wl.order // 2
         if wl.ndim == 2:
-            kname, tag = "k_step2d<R=%d,NSTEP=%d>" % (R, nstep), "k_step2d_x2" if two else "k_step2d"
+            kname = "k_step2d3<R=%d>" % R if nstep == 3 else "k_step2d<R=%d,NSTEP=%d>" % (R, nstep)
+            tag = {3: "k_step2d_x3", 2: "k_step2d_x2", 1: "k_step2d"}[nstep]
         else:
-            kname, tag = ("k_step3d2<R=%d>" % R, "k_step3d2") if two else ("k_step3d<R=%d>" % R, "k_step3d")
+            kname, tag = ("k_step3d2<R=%d>" % R, "k_step3d2") if nstep == 2 else ("k_step3d<R=%d>" % R, "k_step3d")
         if st["launches"]:
             # the paper's leapfrog traffic per shot-point-step, times the steps one launch advances
             bytes_per_launch = nstep * S * npad * stencil_bytes(S)
@@ -335,6 +340,7 @@ def gradient_record(args, wl, steps, warmup, dev, profile=True, default_probe=Fa
                    "block": block or "default", "keep_vbar": keep_vbar, "dtt_side": dtt_side, "imaging": imaging,
                    "overlap_contractions": bool(tpx.get_option(tpx.OPT_OVERLAP_CONTRACTIONS)),
                    "fused_steps_3d": bool(tpx.get_option(tpx.OPT_FUSED_STEPS_3D)),
+                   "max_steps_per_launch_2d": tpx.get_option(tpx.OPT_STEPS_2D),
                    "matrix_core_contractions": matrix_core_use(kind, r, keep_vbar),
                    "padded_points_per_shot": npad, "parallelism": "single-gpu"},
         "gradient": "full-storage (Eq. 3)" if full else "probed (Eq. 4)",

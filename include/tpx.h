@@ -247,10 +247,17 @@ void tpx_job_destroy(tpx_job *job);
  * into the caller's stream before the pass ends (the ring then holds 2b + 3
  * instead of b + 2 slots).  The option changes workspace sizes: set it before
  * sizing a workspace, not between sizing and use. */
-enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2, TPX_OPT_FUSED_STEPS_3D = 3 };
+enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2, TPX_OPT_FUSED_STEPS_3D = 3, TPX_OPT_STEPS_2D = 4 };
 /* TPX_OPT_FUSED_STEPS_3D (default 0): 3D launches advance two leapfrog steps
  * at a time (as 2D launches always do) instead of one.  Results are bitwise
  * the same either way; only speed differs. */
+/* TPX_OPT_STEPS_2D (default 2): the most leapfrog steps one 2D launch
+ * advances, 2 or 3.  Three-step launches (temporal blocking over three levels:
+ * u^{k-1}, u^k and beta read once, three new levels written) are used on
+ * problems with the default tile height; they need their own injection tables
+ * and a plain forward/adjoint ring of six levels instead of four, so the option
+ * changes workspace sizes: set it before sizing a workspace.  Results are
+ * bitwise the same for any setting. */
 /* TPX_OPT_MATRIX_CORES (default 1): the probe contractions of the time
  * blocks are dense products (r x b by b x points) and can run on the matrix
  * cores when r is a multiple of 16: bfloat16 MFMA with each FP32 field value
@@ -286,7 +293,8 @@ enum {
     TPX_KERNEL_ACCUM_FWD = 1, /* forward probe contraction                        */
     TPX_KERNEL_ACCUM_ADJ = 2, /* adjoint probe contraction (or fold)              */
     TPX_KERNEL_ACCUM_FULL = 3,/* full-history imaging term                        */
-    TPX_KERNEL_STEP2 = 4      /* two fused leapfrog steps in one launch (2D)      */
+    TPX_KERNEL_STEP2 = 4,     /* two fused leapfrog steps in one launch           */
+    TPX_KERNEL_STEP3 = 5      /* three fused leapfrog steps in one launch (2D)    */
 };
 void tpx_profile_enable(int32_t on);
 tpx_status tpx_profile_read(int32_t kind, double *total_ms, int64_t *launches);

@@ -340,6 +340,259 @@ __global__ __launch_bounds__(256) void k_step2d(const Layout L, const Physics ph
     const int per_shot = ntx * ntz;
     if (a.do_sample) sample_points<4>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bz * ntx + bx, per_shot);
     if (a.sample_prev) sample_points<4>(L, a.prev + shot * L.shot_floats, a.kp, a.smp, shot, bz * ntx + bx, per_shot);
+    if (a.sample_prev2) sample_points<4>(L, a.prev2 + shot * L.shot_floats, a.kp2, a.smp, shot, bz * ntx + bx, per_shot);
+}
+
+// ---------------------------------------------------------------------------
+// 2D leapfrog, three steps per launch (deeper temporal blocking).
+//
+// A block owns a tile of TZ rows by TX = 64 - 4R columns; lane l of each wave
+// holds column x0 - 2R + l.  Step 1 gives u^{k+1} on the tile plus a 2R-wide
+// halo (rows z0 - 2R .. z0 + TZ + 2R - 1, all 64 lanes), step 2 gives u^{k+2}
+// on the tile plus an R-wide halo, step 3 gives u^{k+3} on the tile.  u^k is
+// staged in LDS with a 3R halo (U); u^{k+1} goes to LDS (V); u^{k+2} is written
+// over U once step 1 has read it.  Each thread owns NQ consecutive tile rows
+// of its column in all three steps (z neighbours from a register copy of the
+// column), R/2 rows of step 2's halo for steps 1 and 2, and R/2 rows of step
+// 1's own halo.  u^{k-1}, u^k and beta are read once for three steps; the
+// three new levels are written on the tile.  Every node is computed with the
+// one-step arithmetic, so the result is bitwise that of three one-step
+// launches.  Injection maps cover the first step's region (64 x (TZ + 4R)
+// nodes from (-2R, -2R)).
+// ---------------------------------------------------------------------------
+template <int R, bool FAST, int TZ>
+__device__ __forceinline__ void step2d3_body(const Layout &L, const Physics &ph, const StepArgs &a, int shot,
+                                             int tile, int x0, int z0, float (*U)[64 + 2 * R],
+                                             float (*V)[64 + 2 * R]) {
+#pragma clang fp contract(off)
+    constexpr int TX = t3x(R);
+    constexpr int SH = TZ + 6 * R;            // staged rows of u^k (from z0 - 3R)
+    constexpr int NQ = TZ / 4;                // tile rows per thread
+    constexpr int NS = (SH + 3) / 4;          // staged rows per thread
+    constexpr int NH = R / 2;                 // halo rows per thread, per halo band (2R rows / 4 waves)
+    constexpr int MAPN = 64 * (TZ + 4 * R);   // nodes of one injection map
+    const int lx = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int G0 = (int)L.G[0], P0 = (int)L.P[0], P2 = (int)L.P[2];
+    const uint32_t span = (uint32_t)(L.shot_floats * 4);
+    const int64_t so = shot * L.shot_floats + XO;
+    const __amdgpu_buffer_rsrc_t rc = buf_rsrc(a.cur + so, span), rp = buf_rsrc(a.prev + so, span);
+    const __amdgpu_buffer_rsrc_t rb = buf_rsrc(a.beta + XO, span);
+    auto rowoff = [&](int z) { return (uint32_t)(z + R) * (uint32_t)G0 * 4u; };   // byte offset of padded row z (< 2^32)
+
+    // stage u^k, rows z0 - 3R .. z0 + TZ + 3R - 1, columns x0 - 3R .. x0 + TX + 3R - 1
+    const int sx = x0 - 3 * R + lx, sx2 = sx + 64;
+    const bool sxin = sx >= 0 && sx < P0, sxin2 = lx < 2 * R && sx2 < P0;
+    const uint32_t ox1 = 4u * (uint32_t)(FAST ? sx : clampi(sx, 0, P0 - 1));
+    const uint32_t ox2 = 4u * (uint32_t)(FAST ? (lx < 2 * R ? sx2 : sx) : clampi(sx2, 0, P0 - 1));
+    float t[NS], t2[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int row = w + 4 * i, gz = z0 - 3 * R + row;
+        const bool zin = FAST || (row < SH && gz >= 0 && gz < P2);
+        const uint32_t ro = rowoff(FAST ? (row < SH ? gz : z0) : clampi(gz, 0, P2 - 1));
+        const float v1 = buf_load(rc, ox1, ro), v2 = buf_load(rc, ox2, ro);
+        t[i] = (zin && (FAST || sxin)) ? v1 : 0.0f;
+        t2[i] = (zin && (FAST || sxin2)) ? v2 : 0.0f;
+    }
+    // u^{k-1} and beta at this thread's nodes: column x; tile rows zb .. zb + NQ - 1,
+    // step 2's halo rows (hz2) and step 1's own halo rows (hz1)
+    const int x = x0 - 2 * R + lx;
+    const bool xin = x >= 0 && x < P0;
+    const uint32_t ox = 4u * (uint32_t)(FAST ? x : clampi(x, 0, P0 - 1));
+    const int zb = z0 + w * NQ;
+    auto hz2 = [&](int i) { const int hr = w + 4 * i; return hr < R ? z0 - R + hr : z0 + TZ + (hr - R); };
+    auto hz1 = [&](int i) { const int hr = w + 4 * i; return hr < R ? z0 - 2 * R + hr : z0 + TZ + R + (hr - R); };
+    float p[NQ], b[NQ], hp2[NH], hb2[NH], hp1[NH], hb1[NH];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int z = zb + q;
+        const uint32_t ro = rowoff(FAST ? z : clampi(z, 0, P2 - 1));
+        const float pv = buf_load(rp, ox, ro), bv = buf_load(rb, ox, ro);
+        const bool ok = FAST || (xin && z < P2);
+        p[q] = ok ? pv : 0.0f;
+        b[q] = ok ? bv : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+        const int z2 = hz2(i), z1 = hz1(i);
+        const uint32_t ro2 = rowoff(FAST ? z2 : clampi(z2, 0, P2 - 1)), ro1 = rowoff(FAST ? z1 : clampi(z1, 0, P2 - 1));
+        const float pv2 = buf_load(rp, ox, ro2), bv2 = buf_load(rb, ox, ro2);
+        const float pv1 = buf_load(rp, ox, ro1), bv1 = buf_load(rb, ox, ro1);
+        const bool ok2 = FAST || (xin && z2 >= 0 && z2 < P2), ok1 = FAST || (xin && z1 >= 0 && z1 < P2);
+        hp2[i] = ok2 ? pv2 : 0.0f;
+        hb2[i] = ok2 ? bv2 : 0.0f;
+        hp1[i] = ok1 ? pv1 : 0.0f;
+        hb1[i] = ok1 ? bv1 : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int row = w + 4 * i;
+        if (row < SH) {
+            U[row][lx] = t[i];
+            if (lx < 2 * R) U[row][64 + lx] = t2[i];
+        }
+    }
+
+    // point sources: each node looks up its segment in the tile's dense map
+    // (map row = z - (z0 - 2R), map column = lane)
+    float s1[NQ], s2[NQ], s3[NQ], sh21[NH], sh22[NH], sh1[NH];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) s1[q] = s2[q] = s3[q] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < NH; ++i) sh21[i] = sh22[i] = sh1[i] = 0.0f;
+    if (a.inject) {
+        const int map = a.inj.tile_dense[tile];
+        if (map >= 0) {
+            const int32_t *dm = a.inj.dense + (int64_t)map * MAPN + lx;
+            const float *amp = a.amp.ptr + shot * a.amp.shot_stride;
+            const float *amp1 = amp + (int64_t)a.k * a.amp.k_stride;
+            const float *amp2 = amp + (int64_t)a.k2 * a.amp.k_stride;
+            const float *amp3 = amp + (int64_t)a.k3 * a.amp.k_stride;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int sg = dm[(w * NQ + q + 2 * R) * 64];
+                if (sg >= 0) {
+                    s1[q] = segment_value(a.inj, amp1, a.amp.scale, sg);
+                    s2[q] = segment_value(a.inj, amp2, a.amp.scale, sg);
+                    s3[q] = segment_value(a.inj, amp3, a.amp.scale, sg);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NH; ++i) {
+                const int sg2 = dm[(hz2(i) - (z0 - 2 * R)) * 64], sg1 = dm[(hz1(i) - (z0 - 2 * R)) * 64];
+                if (sg2 >= 0) {
+                    sh21[i] = segment_value(a.inj, amp1, a.amp.scale, sg2);
+                    sh22[i] = segment_value(a.inj, amp2, a.amp.scale, sg2);
+                }
+                if (sg1 >= 0) sh1[i] = segment_value(a.inj, amp1, a.amp.scale, sg1);
+            }
+        }
+    }
+    __syncthreads();
+
+    const float hx = FAST ? 0.0f : layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
+    auto hdz = [&](int z) { return ph.hd_max * (hx + layer_frac2(z, (int)L.n[2], L.nb, ph.inv_nb)); };
+    // one node of any step: centre, x neighbours of its LDS row, z neighbour pairs zs[k]
+    auto node = [&](float cv, const lds_f32 *row, const float *zs, float prev, float beta, float src, int z) {
+        float lap = 2.0f * ph.c[0] * cv;
+#pragma unroll
+        for (int k = 1; k <= R; ++k) lap = __builtin_fmaf(ph.c[k], (row[R - k] + row[R + k]) + zs[k], lap);
+        if (FAST) return leapfrog0(cv, prev, beta, lap, src);
+        return (xin && z >= 0 && z < P2) ? leapfrog(cv, prev, beta, lap, src, hdz(z)) : 0.0f;
+    };
+
+    // step 1: u^{k+1} on rows z0 - 2R .. z0 + TZ + 2R - 1 into V (row z - (z0 - 2R))
+    float c[NQ], v1[NQ], hc2[NH];
+    {
+        float col[NQ + 2 * R];
+#pragma unroll
+        for (int i = 0; i < NQ + 2 * R; ++i) col[i] = U[w * NQ + 2 * R + i][lx + R];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float zs[R + 1];
+#pragma unroll
+            for (int k = 1; k <= R; ++k) zs[k] = col[q + R - k] + col[q + R + k];
+            const float cv = col[q + R];
+            const float v = node(cv, lds_row(&U[w * NQ + q + 3 * R][lx]), zs, p[q], b[q], s1[q], zb + q);
+            V[w * NQ + q + 2 * R][lx + R] = v;
+            c[q] = cv;
+            v1[q] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+#pragma unroll
+            for (int band = 0; band < 2; ++band) {   // step 2's halo rows, then step 1's own
+                const int z = band == 0 ? hz2(i) : hz1(i);
+                const int ur = z - (z0 - 3 * R);
+                float zs[R + 1];
+#pragma unroll
+                for (int k = 1; k <= R; ++k) zs[k] = U[ur - k][lx + R] + U[ur + k][lx + R];
+                const float cv = U[ur][lx + R];
+                const float v = band == 0 ? node(cv, lds_row(&U[ur][lx]), zs, hp2[i], hb2[i], sh21[i], z)
+                                          : node(cv, lds_row(&U[ur][lx]), zs, hp1[i], hb1[i], sh1[i], z);
+                V[z - (z0 - 2 * R)][lx + R] = v;
+                if (band == 0) hc2[i] = cv;
+            }
+        }
+    }
+    __syncthreads();
+
+    // step 2: u^{k+2} on rows z0 - R .. z0 + TZ + R - 1, written over U (row z - (z0 - R));
+    // lanes outside R .. 63 - R read V's spare columns and are never used
+    float v2[NQ];
+    {
+        float col[NQ + 2 * R];
+#pragma unroll
+        for (int i = 0; i < NQ + 2 * R; ++i) col[i] = V[w * NQ + R + i][lx + R];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            float zs[R + 1];
+#pragma unroll
+            for (int k = 1; k <= R; ++k) zs[k] = col[q + R - k] + col[q + R + k];
+            const float v = node(col[q + R], lds_row(&V[w * NQ + q + 2 * R][lx]), zs, c[q], b[q], s2[q], zb + q);
+            U[w * NQ + q + R][lx + R] = v;
+            v2[q] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < NH; ++i) {
+            const int z = hz2(i), vr = z - (z0 - 2 * R);
+            float zs[R + 1];
+#pragma unroll
+            for (int k = 1; k <= R; ++k) zs[k] = V[vr - k][lx + R] + V[vr + k][lx + R];
+            U[z - (z0 - R)][lx + R] = node(V[vr][lx + R], lds_row(&V[vr][lx]), zs, hc2[i], hb2[i], sh22[i], z);
+        }
+    }
+    __syncthreads();
+
+    // step 3: u^{k+3} on the tile; the three new levels are written there
+    const bool act = lx >= 2 * R && lx < 2 * R + TX && (FAST || x < P0);   // lanes on tile columns
+    const __amdgpu_buffer_rsrc_t rn1 = buf_rsrc(a.next + so, span), rn2 = buf_rsrc(a.next2 + so, span);
+    const __amdgpu_buffer_rsrc_t rn3 = buf_rsrc(a.next3 + so, span);
+    float col[NQ + 2 * R];
+#pragma unroll
+    for (int i = 0; i < NQ + 2 * R; ++i) col[i] = U[w * NQ + i][lx + R];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int z = zb + q;
+        float zs[R + 1];
+#pragma unroll
+        for (int k = 1; k <= R; ++k) zs[k] = col[q + R - k] + col[q + R + k];
+        const float v3 = node(col[q + R], lds_row(&U[w * NQ + q + R][lx]), zs, v1[q], b[q], s3[q], z);
+        if (act && (FAST || z < P2)) {
+            const uint32_t ro = rowoff(z);
+            buf_store(v1[q], rn1, ox, ro);
+            buf_store(v2[q], rn2, ox, ro);
+            buf_store(v3, rn3, ox, ro);
+        }
+    }
+}
+
+template <int R, int TZ>
+__global__ __launch_bounds__(256) void k_step2d3(const Layout L, const Physics ph, const StepArgs a) {
+    constexpr int TX = t3x(R);
+    __shared__ float U[TZ + 6 * R][64 + 2 * R];
+    __shared__ float V[TZ + 4 * R][64 + 2 * R];
+    const int ntx = (int)L.ntiles[0], ntz = (int)L.ntiles[2], nsp = ntx * ntz;
+    const int lid = xcd_logical_block(nsp * L.S);
+    if (lid < 0) return;
+    // shot groups per XCD and shot-adjacent tiles, as in k_step2d
+    const int sg = L.S % 8 == 0 ? L.S / 8 : 1;
+    const int grp = lid / (nsp * sg), rem = lid - grp * (nsp * sg);
+    const int sp = rem / sg, shot = grp * sg + (rem - sp * sg);
+    const int bx = sp % ntx, bz = sp / ntx;
+    const int x0 = bx * TX, z0 = bz * TZ, nb = L.nb;
+    const bool fast = x0 - 3 * R >= 0 && z0 - 3 * R >= 0 && x0 + TX + 3 * R <= (int)L.P[0] &&
+                      z0 + TZ + 3 * R <= (int)L.P[2] && x0 - 2 * R >= nb && z0 - 2 * R >= nb &&
+                      x0 + TX + 2 * R <= nb + (int)L.n[0] && z0 + TZ + 2 * R <= nb + (int)L.n[2];
+    const int tile = (shot * ntz + bz) * ntx + bx;
+    if (fast) step2d3_body<R, true, TZ>(L, ph, a, shot, tile, x0, z0, U, V);
+    else step2d3_body<R, false, TZ>(L, ph, a, shot, tile, x0, z0, U, V);
+
+    const int per_shot = ntx * ntz, bis = bz * ntx + bx;
+    if (a.do_sample) sample_points<4>(L, a.cur + shot * L.shot_floats, a.k, a.smp, shot, bis, per_shot);
+    if (a.sample_prev) sample_points<4>(L, a.prev + shot * L.shot_floats, a.kp, a.smp, shot, bis, per_shot);
+    if (a.sample_prev2) sample_points<4>(L, a.prev2 + shot * L.shot_floats, a.kp2, a.smp, shot, bis, per_shot);
 }
 
 // ---------------------------------------------------------------------------
@@ -923,7 +1176,12 @@ hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hi
             hipLaunchKernelGGL((k_step2d<RR, NS, T2Z_MID>), grid, dim3(256), 0, stream, L, ph, a);  \
         else hipLaunchKernelGGL((k_step2d<RR, NS, T2Z_SMALL>), grid, dim3(256), 0, stream, L, ph, a); \
     } while (0)
-        if (a.nstep == 2) {
+        if (a.nstep == 3) {
+            // L is the three-step layout: tiles of t3x(R) columns and T2Z rows
+            if (tz != T2Z || L.tile[0] != t3x(L.R)) return hipErrorInvalidValue;
+            if (L.R == 2) hipLaunchKernelGGL((k_step2d3<2, T2Z>), grid, dim3(256), 0, stream, L, ph, a);
+            else hipLaunchKernelGGL((k_step2d3<4, T2Z>), grid, dim3(256), 0, stream, L, ph, a);
+        } else if (a.nstep == 2) {
             if (L.R == 2) TPX_STEP2D(2, 2);
             else TPX_STEP2D(4, 2);
         } else {

@@ -127,8 +127,14 @@ void stencil_weights(int order, double c[5]) {
     }
 }
 
+// Most leapfrog steps one 2D launch advances: 2 (default) or 3 (three only
+// with the default tile height; measured no faster inside the gradient).
+std::atomic<int> g_steps2d{2};
+
 struct Problem {
     Layout L;
+    Layout L3;          // 2D: tiles and maps of the three-step kernel (valid when `three`)
+    bool three = false; // 2D launches may advance three steps
     Physics ph;
     int nt;
     double dt;
@@ -199,6 +205,20 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
     for (int a = 0; a < 3; ++a) L.ntiles[a] = (L.P[a] + L.tile[a] - 1) / L.tile[a];
     L.tiles_per_shot = L.ntiles[0] * L.ntiles[1] * L.ntiles[2];
     L.tz3 = 0;
+    P->three = false;
+    if (L.ndim == 2 && L.tile[2] == T2Z && g_steps2d.load() >= 3) {
+        // three-step tiles: t3x(R) columns, maps over the first step's region
+        // (the tile plus 2R on every side)
+        Layout &L3 = P->L3;
+        L3 = L;
+        L3.tile[0] = t3x(L.R);
+        L3.map[2] = T2Z + 4 * L.R;
+        L3.map_org[0] = -2 * L.R;
+        L3.map_org[2] = -2 * L.R;
+        for (int a = 0; a < 3; ++a) L3.ntiles[a] = (L3.P[a] + L3.tile[a] - 1) / L3.tile[a];
+        L3.tiles_per_shot = L3.ntiles[0] * L3.ntiles[1] * L3.ntiles[2];
+        P->three = true;
+    }
     if (L.ndim == 3) {
         // z chunks of the two-step kernel: about 32 planes, shorter when the
         // launch would otherwise hold fewer than 2048 blocks (8 per CU), never
@@ -397,6 +417,7 @@ HostSample add_sample(Blob &b, const Problem &P, const std::vector<Corners> &cs)
 struct Tables {
     Blob blob;
     HostInject src_inj, rec_inj;
+    HostInject src_inj3, rec_inj3;   // three-step layout (2D, when the problem allows it)
     HostSample rec_smp, src_smp;
 };
 
@@ -422,6 +443,16 @@ tpx_status build_tables(const Problem &P, const tpx_grid *g, const tpx_geom *geo
         for (int i = 0; i < P.nrec; ++i) push_corners(P, rec[(size_t)s * P.nrec + i], s, i, er);
     T->src_inj = add_inject(T->blob, P, es);
     T->rec_inj = add_inject(T->blob, P, er);
+    if (P.three) {
+        Problem P3 = P;
+        P3.L = P.L3;
+        std::vector<Entry> es3, er3;
+        for (int s = 0; s < S; ++s) push_corners(P3, src[s], s, 0, es3);
+        for (int s = 0; s < S; ++s)
+            for (int i = 0; i < P.nrec; ++i) push_corners(P3, rec[(size_t)s * P.nrec + i], s, i, er3);
+        T->src_inj3 = add_inject(T->blob, P3, es3);
+        T->rec_inj3 = add_inject(T->blob, P3, er3);
+    }
     T->rec_smp = add_sample(T->blob, P, rec);
     T->rec_smp.n = P.nrec;
     T->src_smp = add_sample(T->blob, P, src);
@@ -553,9 +584,10 @@ Plan make_plan(const Problem &P, Mode mode, const tpx_probe *pr, size_t table_by
     if (probed && pr->block > 0) p.block = std::min(pr->block, P.nt - 1);
     if (mode == M_GRAD_FULL) p.block = std::min(32, P.nt - 1);
     // without contractions the ring holds the four levels a launch of two
-    // fused steps touches.  With contractions a launch never crosses a block
-    // end, so one block plus two levels suffices.
-    p.nslots = plain ? 4 : ring_slots(p.block, p.overlap);
+    // fused steps touches, or six with three-step launches (five touched, and
+    // the middle one the next launch samples).  With contractions a launch
+    // never crosses a block end, so one block plus two levels suffices.
+    p.nslots = plain ? (P.three ? 6 : 4) : ring_slots(p.block, p.overlap);
     const size_t slot = (size_t)L.slot_floats * 4;
     const size_t ntr = (size_t)L.S * P.nt * P.nrec;
     size_t o = 0;
@@ -601,6 +633,7 @@ struct Ctx {
     unsigned char *ws = nullptr;
     hipStream_t stream = nullptr;
     InjectTables src_inj, rec_inj;
+    InjectTables src_inj3, rec_inj3;   // three-step layout
     SampleTables rec_smp, src_smp;  // out/scales filled per use
     float *beta = nullptr;
     float *ring = nullptr;
@@ -776,6 +809,10 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     }
     C.src_inj = dev_inject(tb, T.src_inj);
     C.rec_inj = dev_inject(tb, T.rec_inj);
+    if (C.P.three) {
+        C.src_inj3 = dev_inject(tb, T.src_inj3);
+        C.rec_inj3 = dev_inject(tb, T.rec_inj3);
+    }
     C.rec_smp = dev_sample(tb, T.rec_smp);
     C.src_smp = dev_sample(tb, T.src_smp);
     C.beta = (float *)(C.ws + C.plan.beta);
@@ -829,6 +866,14 @@ struct FwdLoop {
 // are paired.
 bool two_steps_allowed(const Ctx &C) { return C.P.L.ndim == 2 || g_fused3d.load() != 0; }
 
+// Most steps per launch.  A three-step launch touches five consecutive levels
+// and the next launch samples the middle one of its three, so its ring needs
+// at least six slots.
+int max_steps_per_launch(const Ctx &C, int ring_slots_used) {
+    if (!two_steps_allowed(C)) return 1;
+    return C.P.three && ring_slots_used >= 6 ? 3 : 2;
+}
+
 tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
                      float *ubar, int dtt = 0) {
     const Layout &L = C.P.L;
@@ -878,8 +923,11 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
         const int k = f.k;
         const int s = k + 1;
         const bool ovl = f.Z && C.plan.overlap;
-        const bool block_end1 = f.Z && (s - f.s_lo + 1 == C.plan.block || s == nt - 1);
-        const int nstep = (two_steps_allowed(C) && k + 1 <= nt - 2 && n + 2 <= max_steps && !block_end1) ? 2 : 1;
+        // steps in this launch: within the record, the caller's budget and
+        // (with contractions) the current block
+        int64_t lim = std::min<int64_t>(max_steps_per_launch(C, f.ns), std::min<int64_t>(nt - 1 - k, max_steps - n));
+        if (f.Z) lim = std::min<int64_t>(lim, C.plan.block - (s - f.s_lo));
+        const int nstep = (int)std::max<int64_t>(lim, 1);
         if (ovl && s == f.s_lo) {
             tpx_status st = overlap_guard(C, f.blk);
             if (st != TPX_OK) return st;
@@ -887,17 +935,25 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
         a.nstep = nstep;
         a.k = k;
         a.k2 = k + 1;
+        a.k3 = k + 2;
         a.kp = k - 1;
+        a.kp2 = k - 2;
         a.cur = slot_ptr(f.buf, L, f.ns, k);
         a.prev = k == 0 ? a.cur : slot_ptr(f.buf, L, f.ns, k - 1);  // u^{-1} = u^0 = 0
+        a.prev2 = k >= 2 ? slot_ptr(f.buf, L, f.ns, k - 2) : nullptr;
         a.next = slot_ptr(f.buf, L, f.ns, k + 1);
-        a.next2 = nstep == 2 ? slot_ptr(f.buf, L, f.ns, k + 2) : nullptr;
-        // sample every level read here that is not sampled yet
+        a.next2 = nstep >= 2 ? slot_ptr(f.buf, L, f.ns, k + 2) : nullptr;
+        a.next3 = nstep == 3 ? slot_ptr(f.buf, L, f.ns, k + 3) : nullptr;
+        a.inj = nstep == 3 ? C.src_inj3 : C.src_inj;
+        // sample every level read here that is not sampled yet (after a
+        // three-step launch, the level two before `cur` too)
         a.do_sample = f.sample && f.next_row <= k;
         a.sample_prev = f.sample && k >= 1 && f.next_row <= k - 1;
+        a.sample_prev2 = f.sample && k >= 2 && f.next_row <= k - 2;
         if (f.sample) f.next_row = k + 1;
-        const int kind = nstep == 2 ? TPX_KERNEL_STEP2 : TPX_KERNEL_STEP;
-        TPX_HIP(prof(kind, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
+        const int kind = nstep == 3 ? TPX_KERNEL_STEP3 : nstep == 2 ? TPX_KERNEL_STEP2 : TPX_KERNEL_STEP;
+        const Layout &LL = nstep == 3 ? C.P.L3 : L;
+        TPX_HIP(prof(kind, C.stream, [&] { return launch_step(LL, C.P.ph, a, C.stream); }));
         f.k += nstep;
         n += nstep;
         const int s_last = k + nstep;  // last level written
@@ -1019,8 +1075,11 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
     while (b.k >= 1 && n < max_steps) {
         const int k = b.k;
         const bool ovl = accum && C.plan.overlap;
-        const bool block_end1 = accum && (b.s_hi - k + 1 == C.plan.block || k == 1);
-        const int nstep = (two_steps_allowed(C) && k - 1 >= 1 && n + 2 <= max_steps && !block_end1) ? 2 : 1;
+        // steps in this launch: down to k = 1, within the caller's budget and
+        // (with contractions) the current block
+        int64_t lim = std::min<int64_t>(max_steps_per_launch(C, ns), std::min<int64_t>(k, max_steps - n));
+        if (accum) lim = std::min<int64_t>(lim, C.plan.block - (b.s_hi - k));
+        const int nstep = (int)std::max<int64_t>(lim, 1);
         if (ovl && k == b.s_hi) {
             tpx_status st = overlap_guard(C, b.blk);
             if (st != TPX_OK) return st;
@@ -1028,18 +1087,25 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
         a.nstep = nstep;
         a.k = k;
         a.k2 = k - 1;
+        a.k3 = k - 2;
         a.kp = k + 1;
+        a.kp2 = k + 2;
         a.cur = slot_ptr(C.ring, L, ns, k);
         a.prev = slot_ptr(C.ring, L, ns, k + 1);
+        a.prev2 = slot_ptr(C.ring, L, ns, k + 2);
         a.next = slot_ptr(C.ring, L, ns, k - 1);
-        a.next2 = nstep == 2 ? slot_ptr(C.ring, L, ns, k - 2) : nullptr;
+        a.next2 = nstep >= 2 ? slot_ptr(C.ring, L, ns, k - 2) : nullptr;
+        a.next3 = nstep == 3 ? slot_ptr(C.ring, L, ns, k - 3) : nullptr;
+        a.inj = nstep == 3 ? C.rec_inj3 : C.rec_inj;
         // sample every level read here that is not sampled yet (rows nt-1 .. 0)
         const bool smp = o.q_adj != nullptr;
         a.do_sample = smp && b.next_row >= k;
         a.sample_prev = smp && k + 1 <= nt - 1 && b.next_row >= k + 1;
+        a.sample_prev2 = smp && k + 2 <= nt - 1 && b.next_row >= k + 2;
         if (smp) b.next_row = k - 1;
-        const int skind = nstep == 2 ? TPX_KERNEL_STEP2 : TPX_KERNEL_STEP;
-        TPX_HIP(prof(skind, C.stream, [&] { return launch_step(L, C.P.ph, a, C.stream); }));
+        const int skind = nstep == 3 ? TPX_KERNEL_STEP3 : nstep == 2 ? TPX_KERNEL_STEP2 : TPX_KERNEL_STEP;
+        const Layout &LL = nstep == 3 ? C.P.L3 : L;
+        TPX_HIP(prof(skind, C.stream, [&] { return launch_step(LL, C.P.ph, a, C.stream); }));
         b.k -= nstep;
         n += nstep;
         const int k_last = k - nstep + 1;  // last step taken: lambda^{k_last - 1} is known, w^{k_last} can be formed
@@ -1584,6 +1650,11 @@ tpx_status tpx_set_option(int32_t option, int64_t value) {
         g_overlap.store(value ? 1 : 0);
         return TPX_OK;
     }
+    if (option == TPX_OPT_STEPS_2D) {
+        if (value != 2 && value != 3) return fail(TPX_E_INVAL, "TPX_OPT_STEPS_2D takes 2 or 3");
+        g_steps2d.store((int)value);
+        return TPX_OK;
+    }
     if (option == TPX_OPT_FUSED_STEPS_3D) {
         g_fused3d.store(value ? 1 : 0);
         return TPX_OK;
@@ -1600,6 +1671,7 @@ int64_t tpx_get_option(int32_t option) {
     if (option == TPX_OPT_OVERLAP_CONTRACTIONS) return g_overlap.load();
     if (option == TPX_OPT_MATRIX_CORES) return g_mfma.load();
     if (option == TPX_OPT_FUSED_STEPS_3D) return g_fused3d.load();
+    if (option == TPX_OPT_STEPS_2D) return g_steps2d.load();
     return -1;
 }
 

@@ -36,6 +36,10 @@ constexpr int T2Z = 32;
 constexpr int T2Z_MID = 16;
 constexpr int T2Z_SMALL = 8;
 __host__ __device__ constexpr int t2x(int R) { return 64 - 2 * R; }
+// Three-step 2D kernel: T2Z rows by 64 - 4R columns; lane l holds column
+// x0 - 2R + l, so a wave row covers the tile plus a 2R-wide halo (the region
+// of the first of its three steps).
+__host__ __device__ constexpr int t3x(int R) { return 64 - 4 * R; }
 // One-step 3D kernel: blocks of 64 (x) by 8 (y) columns, marching T3Z planes in z.
 constexpr int T3X = 64;
 constexpr int T3Y = 8;
@@ -122,15 +126,20 @@ struct StepArgs {
     const float *cur;   // u^k (slot base, shot 0)
     const float *prev;  // u^{k-1}
     float *next;        // u^{k+1}
-    float *next2;       // u^{k+2} (two-step launches only)
+    float *next2;       // u^{k+2} (launches of two or three steps)
+    float *next3;       // u^{k+3} (three-step launches only)
     const float *beta;  // dt^2 / m_pad, one shot-sized field
-    int nstep;          // 1 or 2
+    const float *prev2; // the level before `prev` (sampled only)
+    int nstep;          // 1, 2 or 3 (3: 2D only)
     int k;              // time index of `cur`: amplitudes of the first step, sample row of `cur`
     int k2;             // amplitude index of the second step
+    int k3;             // amplitude index of the third step
     int kp;             // time index of `prev` (its sample row)
+    int kp2;            // time index of `prev2` (its sample row)
     int inject;         // 0/1
     int do_sample;      // 0/1: sample `cur` at row k
     int sample_prev;    // 0/1: sample `prev` at row kp
+    int sample_prev2;   // 0/1: sample `prev2` at row kp2 (the middle level of a three-step launch)
     InjectTables inj;
     Amplitude amp;
     SampleTables smp;

@@ -492,10 +492,11 @@ class Job:
             pass
 
 
-KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL, KERNEL_STEP2 = range(5)
+KERNEL_STEP, KERNEL_ACCUM_FWD, KERNEL_ACCUM_ADJ, KERNEL_ACCUM_FULL, KERNEL_STEP2, KERNEL_STEP3 = range(6)
 OPT_OVERLAP_CONTRACTIONS = 1
 OPT_MATRIX_CORES = 2
 OPT_FUSED_STEPS_3D = 3
+OPT_STEPS_2D = 4
 
 
 def set_option(option: int, value: int):
