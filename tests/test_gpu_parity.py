@@ -523,6 +523,54 @@ def test_c3_full_grid_truncated_record(src):
         assert abs(float(J_g.item()) - J_o) <= TOL * J_o
 
 
+def test_c3_full_grid_dot_test_and_whole_gradient():
+    # Properties that hold at any size, on the full 401 x 401 x 301 grid over
+    # every tile, z chunk and damped face of both 3D step kernels: four shots at
+    # depths in the first, middle and last chunks, receivers on a lattice every
+    # 24 nodes through the whole volume, faces included (4536 of them), a
+    # 60-step record.
+    # - adjoint dot test <F q, d> = <q, F^T d> with random q and d;
+    # - the whole probed gradient and all traces, one-step against two-step
+    #   launches, bit for bit.
+    import torch
+    _print_case("c3_dot_whole")
+    wl = workload("c3_layered_3d").with_(nt=60)
+    h = wl.h
+    nz, ny, nx = wl.shape
+    src = [(2500.0, 2500.0, 60.0), (4987.5, 12.5, 1875.0), (30.0, 4970.0, 3740.0), (1250.0, 3750.0, 2500.0)]
+    lat = lambda n: [i * h for i in range(0, n, 24)] + ([(n - 1) * h] if (n - 1) % 24 else [])
+    rec = [(x, y, z) for z in lat(nz) for y in lat(ny) for x in lat(nx)]
+    wl = wl.with_(src=src, rec=rec)
+    c = Case(wl)
+    rng = np.random.default_rng(12)
+    S, nt, nrec = wl.nshots, wl.nt, len(rec)
+    q = rng.normal(size=(S, nt)).astype(np.float32)
+    d_in = rng.normal(size=(S, nt, nrec)).astype(np.float32)
+    geom_q = tpx.Geometry(c.src, c.rec, cuda(q))
+    m = cuda(c.m_true)
+    Fq = to_np(tpx.forward(c.tgrid(), geom_q, m))
+    FTd = to_np(tpx.adjoint(c.tgrid(), geom_q, m, cuda(d_in)))
+    lhs, rhs = float(np.sum(Fq * d_in.astype(np.float64))), float(np.sum(q.astype(np.float64) * FTd))
+    print(f"[c3_dot] receivers {nrec}, <Fq,d> {lhs:.6e}, <q,F^T d> {rhs:.6e}", flush=True)
+    assert abs(lhs) > 0 and abs(lhs - rhs) <= 1e-4 * abs(lhs)
+    # whole gradient and traces: one-step against two-step launches
+    dobs = cuda(np.zeros((S, nt, nrec), dtype=np.float32))
+    out = []
+    for fused in (0, 1):
+        try:
+            tpx.set_option(tpx.OPT_FUSED_STEPS_3D, fused)
+            d_g = tpx.forward(c.tgrid(), c.tgeom(), m)
+            g_g, J_g = tpx.gradient_probed(c.tgrid(), c.tgeom(), tpx.Probe(r=8, seed=3), cuda(c.m0), dobs)
+            torch.cuda.synchronize()
+        finally:
+            tpx.set_option(tpx.OPT_FUSED_STEPS_3D, 0)
+        out.append((d_g, g_g, float(J_g.item())))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1]) and out[0][2] == out[1][2]
+    nz_frac = float((out[0][1] != 0).float().mean().item())
+    print(f"[c3_dot] gradient nonzero fraction {nz_frac:.3f}", flush=True)
+    assert nz_frac > 0.01
+
+
 def test_largest_2d_shot_fields():
     # Two shots of 5,200,000 x 100 nodes: each padded shot field holds 1.0e9
     # floats (93% of the 2^30 limit), so in-shot byte offsets pass 2^31 and the
