@@ -61,7 +61,7 @@ def parse():
                     help="serving mix instead: continuous batching vs one-at-a-time on one Poisson trace")
     ap.add_argument("--requests", type=int, default=60, help="requests in the serving trace")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget of the server")
-    ap.add_argument("--chunk-steps", type=int, default=128, help="time steps a served job advances per turn")
+    ap.add_argument("--chunk-steps", type=int, default=64, help="time steps a served job advances per turn")
     ap.add_argument("--max-active", type=int, default=4,
                     help="jobs the server keeps on the GPU at once (default: one per hardware queue)")
     ap.add_argument("--inflight", type=int, default=2, help="chunks each served job keeps queued")

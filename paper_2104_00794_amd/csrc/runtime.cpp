@@ -708,7 +708,9 @@ SampleTables dev_sample(unsigned char *base, const HostSample &h) {
 // Host-to-device upload of the geometry tables without waiting for the
 // stream: the bytes are staged in pinned host memory owned by the library and
 // a staging buffer is reused only after the event recorded behind its copy has
-// completed.
+// completed.  Buffers are never freed here (freeing pinned memory waits for
+// the device): a copy takes the smallest idle buffer that holds it, else a new
+// buffer of the next power-of-two size joins the pool.
 struct Staging {
     void *host = nullptr;
     size_t cap = 0;
@@ -738,29 +740,23 @@ hipError_t upload_async(void *dst, const void *src, size_t n, hipStream_t stream
     }
     Staging *use = nullptr;
     for (Staging &st : g_stage) {
-        if (hipEventQuery(st.done) != hipSuccess) continue;   // copy still pending
-        if (st.cap >= n) {
-            use = &st;
-            break;
-        }
-        if (!use) use = &st;   // idle but small: grow it
+        if (st.cap < n || hipEventQuery(st.done) != hipSuccess) continue;   // too small, or copy pending
+        if (!use || st.cap < use->cap) use = &st;
     }
     if (!use) {
-        g_stage.emplace_back();
-        use = &g_stage.back();
-        hipError_t e = hipEventCreateWithFlags(&use->done, hipEventDisableTiming);
+        size_t cap = 4096;
+        while (cap < n) cap *= 2;
+        Staging fresh;
+        hipError_t e = hipHostMalloc(&fresh.host, cap, hipHostMallocDefault);
         if (e != hipSuccess) return e;
-    }
-    if (use->cap < n) {
-        if (use->host) {
-            hipError_t e = hipHostFree(use->host);
-            if (e != hipSuccess) return e;
-            use->host = nullptr;
-            use->cap = 0;
+        fresh.cap = cap;
+        e = hipEventCreateWithFlags(&fresh.done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            (void)hipHostFree(fresh.host);
+            return e;
         }
-        hipError_t e = hipHostMalloc(&use->host, n, hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        use->cap = n;
+        g_stage.push_back(fresh);
+        use = &g_stage.back();
     }
     memcpy(use->host, src, n);
     hipError_t e = hipMemcpyAsync(dst, use->host, n, hipMemcpyHostToDevice, stream);

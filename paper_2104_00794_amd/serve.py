@@ -13,8 +13,14 @@ A request may be withdrawn (``Request.cancel_at``): waiting, it leaves the
 queue; running, it stops advancing and its workspace is freed as soon as the
 chunks already queued on its stream have run, without touching the others.
 
+Job workspaces come from one device arena allocated when ``run`` starts
+(``Arena``: first fit, coalescing frees), so no device allocation happens while
+jobs run: a device allocation can wait for the GPU to drain, and measured
+stalls of up to 0.75 s in the host loop otherwise.
+
 ``run_sequential`` is the plain path: one ``tpx_gradient_probed`` call at a
-time in arrival order, on the same arrival trace.
+time in arrival order, on the same arrival trace, with one workspace of the
+largest size allocated beforehand and reused.
 """
 from __future__ import annotations
 
@@ -56,6 +62,51 @@ def admission_plan(waiting: Sequence, slots: int, free_bytes: float, budget: flo
     return admit, reject
 
 
+class Arena:
+    """One device allocation carved into workspaces: first fit over a free list
+    kept in address order, adjacent free blocks merged on release.  Offsets
+    and sizes are multiples of ALIGN bytes."""
+    ALIGN = 4096
+
+    def __init__(self, nbytes: int, device=None, buf=None):
+        self.size = -(-int(nbytes) // self.ALIGN) * self.ALIGN
+        self.buf = buf if buf is not None else torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free = [(0, self.size)] if self.size > 0 else []   # (offset, bytes), by offset
+
+    def _round(self, n: int) -> int:
+        return max(self.ALIGN, -(-int(n) // self.ALIGN) * self.ALIGN)
+
+    def alloc(self, nbytes: int):
+        """(offset, a uint8 view of nbytes) of the first free block that fits, or None."""
+        n = self._round(nbytes)
+        for i, (off, ln) in enumerate(self.free):
+            if ln >= n:
+                if ln == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + n, ln - n)
+                return off, self.buf[off:off + int(nbytes)]
+        return None
+
+    def release(self, off: int, nbytes: int):
+        n = self._round(nbytes)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        if (i > 0 and self.free[i - 1][0] + self.free[i - 1][1] > off) or (i < len(self.free) and off + n > self.free[i][0]):
+            raise ValueError("release of a block that overlaps free space")
+        self.free.insert(i, (off, n))
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:       # merge with the next block
+            self.free[i] = (off, n + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == off:     # and with the previous one
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def free_bytes(self) -> int:
+        return sum(ln for _, ln in self.free)
+
+
 @dataclass
 class Request:
     rid: int
@@ -93,8 +144,9 @@ class Result:
 
 
 class _Active:
-    def __init__(self, req: Request, job: tpx.Job, stream, need: int, admitted: float):
+    def __init__(self, req: Request, job: tpx.Job, stream, need: int, admitted: float, ws_off: int, ws_bytes: int):
         self.req, self.job, self.stream, self.need, self.admitted = req, job, stream, need, admitted
+        self.ws_off, self.ws_bytes = ws_off, ws_bytes
         self.events = collections.deque()
         self.cancelled = False
 
@@ -112,7 +164,7 @@ class Server:
     admitted in arrival order, a blocked large request letting smaller ones
     behind it pass."""
 
-    def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 128, max_active: int = 4,
+    def __init__(self, hbm_budget_bytes: float = 200e9, chunk_steps: int = 64, max_active: int = 4,
                  nstreams: int = 8, inflight: int = 2, device=None, large_points: float = 3e6, max_large: int = 2):
         self.large_points = float(large_points)
         self.max_large = int(max_large)
@@ -136,6 +188,11 @@ class Server:
         used = 0
         wsb: Dict[int, int] = {}   # workspace bytes per request (sizing builds the tables: done once)
         results: Dict[int, Result] = {}
+        # the workspaces' arena: the budget, or less when all requests together need less
+        for r in reqs:   # sizing builds the tables: before the clock starts
+            wsb[r.rid] = r.workspace_bytes()
+        total_ws = sum(wsb.values())
+        arena = Arena(min(self.budget, total_ws + Arena.ALIGN * len(reqs)), device=self.device)
         t0 = time.perf_counter()
         while pend or waiting or active:
             now = time.perf_counter() - t0
@@ -168,15 +225,18 @@ class Server:
                 results[req.rid].status = "rejected: workspace exceeds the HBM budget"
                 results[req.rid].finished = now
             for req in admit:
+                got = arena.alloc(wsb[req.rid])
+                if got is None:
+                    break   # fragmented: this request and the later ones wait for a release
+                ws_off, ws = got
                 waiting.remove(req)
                 nlarge += 1 if self._large(req) else 0
                 stream = free_streams.pop()
                 # the job's inputs (m, d_obs) come from the caller's stream
                 stream.wait_stream(torch.cuda.current_stream(self.device))
                 with torch.cuda.stream(stream):
-                    ws = torch.empty(wsb[req.rid], dtype=torch.uint8, device=self.device)
                     job = tpx.Job(req.grid, req.geom, req.probe, req.m, req.d_obs, ws=ws, stream=stream)
-                active.append(_Active(req, job, stream, need(req), now))
+                active.append(_Active(req, job, stream, need(req), now, ws_off, wsb[req.rid]))
                 results[req.rid].admitted = now
                 used += need(req)
                 self.peak_active = max(self.peak_active, len(active))
@@ -194,6 +254,7 @@ class Server:
                             res.g, res.J = st.job.g, st.job.J
                         st.job.close()
                         st.job.ws = None
+                        arena.release(st.ws_off, st.ws_bytes)   # its chunks have run
                         active.remove(st)
                         free_streams.append(st.stream)
                         used -= st.need
@@ -223,13 +284,16 @@ def run_sequential(requests: List[Request], device=None) -> Dict[int, Result]:
     reqs = sorted(requests, key=lambda r: r.arrival)
     results: Dict[int, Result] = {}
     stream = torch.cuda.current_stream(device)
+    wsb = {q.rid: q.workspace_bytes() for q in reqs}   # sizing builds the tables: before the clock starts
+    ws_all = torch.empty(max(list(wsb.values()) + [1]), dtype=torch.uint8, device=device)
     t0 = time.perf_counter()
     for req in reqs:
         now = time.perf_counter() - t0
         if req.arrival > now:
             time.sleep(req.arrival - now)
         res = Result(req.rid, req.arrival, admitted=time.perf_counter() - t0)
-        g, J = tpx.gradient_probed(req.grid, req.geom, req.probe, req.m, req.d_obs, stream=stream)
+        ws = ws_all[:wsb[req.rid]]
+        g, J = tpx.gradient_probed(req.grid, req.geom, req.probe, req.m, req.d_obs, ws=ws, stream=stream)
         torch.cuda.synchronize(device)
         res.finished = time.perf_counter() - t0
         res.g, res.J = g, J
