@@ -188,11 +188,14 @@ class Server:
         used = 0
         wsb: Dict[int, int] = {}   # workspace bytes per request (sizing builds the tables: done once)
         results: Dict[int, Result] = {}
-        # the workspaces' arena: the budget, or less when all requests together need less
+        # the workspaces' arena: at most max_active jobs hold workspace at once, so
+        # twice the largest max_active workspaces (slack for fragmentation), never
+        # less than the largest one, never more than the budget
         for r in reqs:   # sizing builds the tables: before the clock starts
             wsb[r.rid] = r.workspace_bytes()
-        total_ws = sum(wsb.values())
-        arena = Arena(min(self.budget, total_ws + Arena.ALIGN * len(reqs)), device=self.device)
+        sizes = sorted(wsb.values(), reverse=True)
+        want = max(2 * sum(sizes[:self.max_active]), sizes[0] if sizes else 0) + Arena.ALIGN * self.max_active
+        arena = Arena(min(self.budget, want), device=self.device)
         t0 = time.perf_counter()
         while pend or waiting or active:
             now = time.perf_counter() - t0
