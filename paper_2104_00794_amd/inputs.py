@@ -224,6 +224,12 @@ def workload(name: str) -> Workload:
         return Workload(name, (301, 401, 401), 12.5, 8, 1.25, 2001, 0.012, 1.5, 4.0,
                         r=32, probe="rademacher", probe_seed=32, model_seed=31, smooth_sigma=10.0,
                         src=[(2500.0, 2500.0, 50.0)], rec=_grid_spread(0.0, 5000.0, 25.0, 50.0))
+    if name == "c4_layered_3d_201":
+        # the serving mix's 3D request shape on its own: 201^3 at 12.5 m, 1 shot,
+        # order 8, 12 Hz, 2 s, r = 32; receivers every 50 m at 25 m depth
+        return Workload(name, (201, 201, 201), 12.5, 8, 1.25, 1601, 0.012, 1.5, 4.0,
+                        r=32, probe="rademacher", probe_seed=52, model_seed=51, smooth_sigma=10.0,
+                        src=[(1250.0, 1250.0, 25.0)], rec=_grid_spread(0.0, 2500.0, 50.0, 25.0))
     if name == "f4_fwi_2d":
         # The inversion experiment's shape on C1's grid and model: 49 shots 200 m
         # apart at 50 m depth, ocean-bottom receivers 50 m apart at 500 m depth,
@@ -235,7 +241,7 @@ def workload(name: str) -> Workload:
     raise KeyError(name)
 
 
-WORKLOADS = ("c0_two_layer_2d", "c1_layered_2d_16shots", "c2_autograd_2d", "c3_layered_3d", "f4_fwi_2d")
+WORKLOADS = ("c0_two_layer_2d", "c1_layered_2d_16shots", "c2_autograd_2d", "c3_layered_3d", "c4_layered_3d_201", "f4_fwi_2d")
 
 
 def small_2d(nz=40, nx=48, h=10.0, order=8, nt=180, nbl=6, nshots=2, nrec=9, seed=5, r=8,
