@@ -141,3 +141,29 @@ def test_steps_option_is_validated():
     with pytest.raises(tpx.TpxError):
         tpx.set_option(tpx.OPT_STEPS_2D, 4)
     assert tpx.get_option(tpx.OPT_STEPS_2D) == 3
+
+
+@pytest.mark.parametrize("block", [7, 16])
+def test_three_steps_with_overlapped_contractions(block):
+    # contractions on the auxiliary stream (ring of 2b + 3 slots) together with
+    # three-step launches: the gradient is bitwise that of serial contractions
+    # with two-step launches
+    import torch
+    print(f"[three_step] overlap block={block}", flush=True)
+    c = _case(order=8, nt=90, edge_sources=True)
+    dobs = c.dobs_oracle()
+    tg, geom, m, d = c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs)
+    probe = tpx.Probe(r=8, seed=2, block=block)
+    g3, J3 = tpx.gradient_probed(tg, geom, probe, m, d)
+    try:
+        tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 1)
+        g3o, J3o = tpx.gradient_probed(tg, geom, probe, m, d)
+        tpx.set_option(tpx.OPT_STEPS_2D, 2)
+        tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 0)
+        g2, J2 = tpx.gradient_probed(tg, geom, probe, m, d)
+    finally:
+        tpx.set_option(tpx.OPT_OVERLAP_CONTRACTIONS, 0)
+        tpx.set_option(tpx.OPT_STEPS_2D, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(g3, g3o) and torch.equal(J3, J3o)
+    assert torch.equal(g3, g2) and torch.equal(J3, J2)
