@@ -83,6 +83,15 @@ __device__ __forceinline__ int xcd_logical_block(int nlogical) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// First column past the 128-byte line that holds a row's last padded node.  The
+// row's pitch always reaches it (G0 is a multiple of 32 floats and at least
+// XO + P0 + R), and the columns between P0 and it are ghost columns, which no
+// kernel reads as data (every load there is masked).  The 2D step kernels store
+// zeros there: a line written only in part costs the memory a read-modify-write
+// (measured: a quarter longer for the whole write stream of a 16-shot 841-node-
+// wide tile pass), whole lines are written straight.
+__device__ __forceinline__ int row_store_end(int P0) { return ((XO + P0 + 31) & ~31) - XO; }
+
 // Raw buffer access: a descriptor per array (scalar registers), a 32-bit byte
 // offset per lane and a wave-uniform byte offset per row (scalar), so row
 // addressing costs no vector instructions.  Accesses past `bytes` read zero
@@ -234,7 +243,11 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
 
     // first step on this thread's rows
     const float hx = FAST ? 0.0f : layer_frac2(x, (int)L.n[0], L.nb, ph.inv_nb);
-    const bool act = lx >= R && lx < R + TX && (FAST || x < P0);   // lanes on tile columns
+    // lanes on tile columns; past the box they store zeros up to the end of the
+    // row's last 128-byte line (ghost columns), so the memory sees whole lines
+    // instead of a partial one that costs a read-modify-write
+    const bool act = lx >= R && lx < R + TX && (FAST || x < row_store_end(P0));
+    const uint32_t os = 4u * (uint32_t)x;   // unclamped: x >= 0 on tile lanes
     const __amdgpu_buffer_rsrc_t rn1 = buf_rsrc(a.next + so, span);
     float c[NQ], hd[NQ];
     {
@@ -258,7 +271,7 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
                 v = (xin && z < P2) ? leapfrog(cv, p[q], b[q], lap, s1[q], hd[q]) : 0.0f;
             }
             if (NSTEP == 1) {
-                if (act && (FAST || z < P2)) buf_store(v, rn1, ox, rowoff(z));
+                if (act && (FAST || z < P2)) buf_store(v, rn1, os, rowoff(z));
             } else {
                 V[w * NQ + q + R][lx + R] = v;
             }
@@ -308,8 +321,9 @@ __device__ __forceinline__ void step2d_body(const Layout &L, const Physics &ph, 
             lap = __builtin_fmaf(ph.c[k], (vp[R - k] + vp[R + k]) + (col[q + R - k] + col[q + R + k]), lap);
         if (act && (FAST || z < P2)) {
             const uint32_t ro = rowoff(z);
-            buf_store(v, rn1, ox, ro);
-            buf_store(FAST ? leapfrog0(v, c[q], b[q], lap, s2[q]) : leapfrog(v, c[q], b[q], lap, s2[q], hd[q]), rn2, ox, ro);
+            buf_store(v, rn1, os, ro);
+            buf_store(FAST ? leapfrog0(v, c[q], b[q], lap, s2[q]) : (xin ? leapfrog(v, c[q], b[q], lap, s2[q], hd[q]) : 0.0f),
+                      rn2, os, ro);
         }
     }
 }
@@ -546,7 +560,10 @@ __device__ __forceinline__ void step2d3_body(const Layout &L, const Physics &ph,
     __syncthreads();
 
     // step 3: u^{k+3} on the tile; the three new levels are written there
-    const bool act = lx >= 2 * R && lx < 2 * R + TX && (FAST || x < P0);   // lanes on tile columns
+    // lanes on tile columns, and past the box up to the end of the row's last
+    // 128-byte line (zeros into ghost columns, as in the two-step kernel)
+    const bool act = lx >= 2 * R && lx < 2 * R + TX && (FAST || x < row_store_end(P0));
+    const uint32_t os = 4u * (uint32_t)x;
     const __amdgpu_buffer_rsrc_t rn1 = buf_rsrc(a.next + so, span), rn2 = buf_rsrc(a.next2 + so, span);
     const __amdgpu_buffer_rsrc_t rn3 = buf_rsrc(a.next3 + so, span);
     float col[NQ + 2 * R];
@@ -561,9 +578,9 @@ __device__ __forceinline__ void step2d3_body(const Layout &L, const Physics &ph,
         const float v3 = node(col[q + R], lds_row(&U[w * NQ + q + R][lx]), zs, v1[q], b[q], s3[q], z);
         if (act && (FAST || z < P2)) {
             const uint32_t ro = rowoff(z);
-            buf_store(v1[q], rn1, ox, ro);
-            buf_store(v2[q], rn2, ox, ro);
-            buf_store(v3, rn3, ox, ro);
+            buf_store(v1[q], rn1, os, ro);
+            buf_store(v2[q], rn2, os, ro);
+            buf_store(v3, rn3, os, ro);
         }
     }
 }
