@@ -286,14 +286,48 @@ bool corners_of(const Problem &P, const tpx_grid *g, const double pos[3], Corner
     return true;
 }
 
+// Host image of the tables, uploaded into the workspace at set-up.  The dense
+// injection maps of a large problem run to megabytes, and fresh memory of that
+// size costs a page fault per 4 KiB page on every call, all of it before the
+// call's first launch.  So each thread keeps one blob's storage between calls
+// (up to kBlobKeep bytes); a second blob alive on the same thread at the same
+// time gets storage of its own.
+constexpr size_t kBlobKeep = size_t(64) << 20;
+thread_local std::vector<unsigned char> tl_blob;
+thread_local bool tl_blob_busy = false;
+
 struct Blob {
-    std::vector<unsigned char> bytes;
-    size_t put(const void *p, size_t n) {
-        const size_t off = bytes.size();
-        bytes.resize(align_up(off + n));
-        if (n) memcpy(bytes.data() + off, p, n);
+    std::vector<unsigned char> own;
+    std::vector<unsigned char> *buf;
+    size_t size = 0;   // bytes in use (each part starts kAlign-aligned)
+    bool borrowed = false;
+    Blob() : buf(&own) {
+        if (!tl_blob_busy) {
+            tl_blob_busy = borrowed = true;
+            buf = &tl_blob;
+        }
+    }
+    ~Blob() {
+        if (!borrowed) return;
+        if (tl_blob.capacity() > kBlobKeep) std::vector<unsigned char>().swap(tl_blob);
+        tl_blob_busy = false;
+    }
+    Blob(const Blob &) = delete;
+    Blob &operator=(const Blob &) = delete;
+    // n more bytes at an aligned offset, which is returned; contents undefined
+    size_t grow(size_t n) {
+        const size_t off = size;
+        size = align_up(off + n);
+        if (buf->size() < size) buf->resize(std::max(size, buf->size() + buf->size() / 2));
         return off;
     }
+    size_t put(const void *p, size_t n) {
+        const size_t off = grow(n);
+        if (n) memcpy(buf->data() + off, p, n);
+        return off;
+    }
+    unsigned char *data() { return buf->data(); }
+    bool empty() const { return size == 0; }
 };
 
 struct HostInject {  // offsets into the blob
@@ -325,16 +359,22 @@ HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
     });
     const int64_t ntile = (int64_t)L.S * L.tiles_per_shot;
     const int64_t tp = (int64_t)L.map[0] * L.map[1] * L.map[2];
-    std::vector<int32_t> tile_dense(ntile, -1), dense, seg_ent, ent_idx;
+    std::vector<int32_t> tile_dense(ntile, -1), seg_ent, ent_idx;
     std::vector<float> ent_w;
-    int32_t nseg = 0;
+    seg_ent.reserve(ent.size() + 1);
+    ent_idx.reserve(ent.size());
+    ent_w.reserve(ent.size());
+    // the dense maps are written straight into the blob
+    int64_t nmaps = 0;
+    for (size_t i = 0; i < ent.size(); ++i) nmaps += i == 0 || ent[i].tile != ent[i - 1].tile;
+    const size_t dense_off = b.grow((size_t)(nmaps * tp) * 4);
+    int32_t *dense = (int32_t *)(b.data() + dense_off);   // valid until the next grow
+    std::fill(dense, dense + nmaps * tp, -1);
+    int32_t nseg = 0, nmap = 0;
     for (size_t i = 0; i < ent.size(); ++i) {
         const bool new_tile = i == 0 || ent[i].tile != ent[i - 1].tile;
         const bool new_seg = new_tile || ent[i].local != ent[i - 1].local;
-        if (new_tile) {
-            tile_dense[ent[i].tile] = (int32_t)(dense.size() / tp);
-            dense.resize(dense.size() + tp, -1);
-        }
+        if (new_tile) tile_dense[ent[i].tile] = nmap++;
         if (new_seg) {
             dense[(size_t)tile_dense[ent[i].tile] * tp + ent[i].local] = nseg++;
             seg_ent.push_back((int32_t)i);
@@ -359,7 +399,7 @@ HostInject add_inject(Blob &b, const Problem &P, std::vector<Entry> &ent) {
     HostInject h;
     h.col_z = b.put(col_z.data(), col_z.size() * 4);
     h.tile_dense = b.put(tile_dense.data(), tile_dense.size() * 4);
-    h.dense = b.put(dense.data(), dense.size() * 4);
+    h.dense = dense_off;
     h.seg_ent = b.put(seg_ent.data(), seg_ent.size() * 4);
     h.ent_idx = b.put(ent_idx.data(), ent_idx.size() * 4);
     h.ent_w = b.put(ent_w.data(), ent_w.size() * 4);
@@ -783,7 +823,7 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     Tables T;
     st = build_tables(C.P, g, geo, &T);
     if (st != TPX_OK) return st;
-    C.plan = make_plan(C.P, mode, pr, T.blob.bytes.size(), !C.no_alloc);
+    C.plan = make_plan(C.P, mode, pr, T.blob.size, !C.no_alloc);
     if (!ws || ws_bytes < C.plan.total) {
         char buf[160];
         snprintf(buf, sizeof buf, "workspace of %zu bytes is smaller than the %zu bytes required", ws_bytes,
@@ -793,14 +833,14 @@ tpx_status setup(Ctx &C, const tpx_grid *g, const tpx_geom *geo, const tpx_probe
     C.ws = (unsigned char *)ws;
     C.stream = (hipStream_t)stream;
     unsigned char *tb = C.ws + C.plan.tables;
-    if (!T.blob.bytes.empty()) {
+    if (!T.blob.empty()) {
         if (C.no_alloc) {
             // no pinned staging: copy from the tables' own (pageable) memory and
             // wait for the copy before that memory is released
-            TPX_HIP(hipMemcpyAsync(tb, T.blob.bytes.data(), T.blob.bytes.size(), hipMemcpyHostToDevice, C.stream));
+            TPX_HIP(hipMemcpyAsync(tb, T.blob.data(), T.blob.size, hipMemcpyHostToDevice, C.stream));
             TPX_HIP(hipStreamSynchronize(C.stream));
         } else {
-            TPX_HIP(upload_async(tb, T.blob.bytes.data(), T.blob.bytes.size(), C.stream));
+            TPX_HIP(upload_async(tb, T.blob.data(), T.blob.size, C.stream));
         }
     }
     C.src_inj = dev_inject(tb, T.src_inj);
@@ -1369,7 +1409,7 @@ tpx_status gradient_probed_in_scratch(const tpx_grid *grid, const tpx_geom *geom
         if ((st = check_probe(P, probe)) != TPX_OK) return st;
         Tables T;
         if ((st = build_tables(P, grid, geom, &T)) != TPX_OK) return st;
-        const size_t need = make_plan(P, M_GRAD_PROBED, probe, T.blob.bytes.size(), false).total;
+        const size_t need = make_plan(P, M_GRAD_PROBED, probe, T.blob.size, false).total;
         if (need > scratch_bytes) {
             char buf[200];
             snprintf(buf, sizeof buf,
@@ -1408,7 +1448,7 @@ size_t tpx_workspace_bytes(int32_t call, const tpx_grid *grid, const tpx_geom *g
             return fail(TPX_E_INVAL, "range-finder probes need d_obs: pass tpx_range_finder_probes' Q as EXPLICIT");
         Tables T;
         if ((st = build_tables(P, grid, geom, &T)) != TPX_OK) return st;
-        out = make_plan(P, mode, probe, T.blob.bytes.size()).total;
+        out = make_plan(P, mode, probe, T.blob.size).total;
         return TPX_OK;
     });
     return out;

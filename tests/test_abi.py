@@ -204,3 +204,31 @@ def test_binding_checks_tensors_before_any_call():
         tpx.gradient_probed(grid, geom, tpx.Probe(r=4), m_cpu, torch.zeros(1, 100, 1))
     with pytest.raises(TypeError):
         tpx.gradient_full(grid, geom, torch.ones(30, 40, dtype=torch.float64), torch.zeros(1, 100, 1))
+
+
+def test_table_sizes_do_not_depend_on_earlier_calls():
+    # The host image of the injection tables reuses its storage between calls on
+    # a thread.  Workspace sizes (which include the tables) must depend on the
+    # problem only: a large receiver spread (megabytes of dense maps) and a small
+    # one, queried in either order and under both 2D launch depths, give the
+    # same answers every time.
+    from paper_2104_00794_amd.inputs import workload
+    wl = workload("c1_layered_2d_16shots")
+    big_g = tpx.Grid(wl.shape, h=wl.h, dt=wl.dt, nt=wl.nt, order=wl.order, nbl=wl.nbl, damp_vmax=wl.vmax)
+    big = (big_g, tpx.Geometry(wl.src_pos(), wl.rec_pos()), tpx.Probe(r=16))
+    small = (tpx.Grid(**GRID), _geom([[100.0, 0, 50.0]], [[[10.0, 0, 20.0]] * 3]), tpx.Probe(r=8))
+    calls = (tpx.CALL_FORWARD, tpx.CALL_GRADIENT_PROBED)
+    old = tpx.get_option(tpx.OPT_STEPS_2D)
+    try:
+        seen = {}
+        for steps in (3, 2, 3, 2):
+            tpx.set_option(tpx.OPT_STEPS_2D, steps)
+            for name, (g, geo, p) in (("big", big), ("small", small), ("big", big), ("small", small)):
+                for call in calls:
+                    n = tpx.workspace_bytes(call, g, geo, p)
+                    assert n > 0
+                    assert seen.setdefault((steps, name, call), n) == n, (steps, name, call)
+        # the three-step layout adds its own tables (and two plain-pass slots)
+        assert seen[(3, "big", tpx.CALL_GRADIENT_PROBED)] > seen[(2, "big", tpx.CALL_GRADIENT_PROBED)]
+    finally:
+        tpx.set_option(tpx.OPT_STEPS_2D, old)

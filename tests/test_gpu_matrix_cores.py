@@ -117,6 +117,8 @@ def test_split_probes_on_the_matrix_cores_match_oracle(r, keep_vbar, side):
     assert rel_l2(to_np(g_m), to_np(g_v)) <= 1e-5
 
 
+# the FP64 oracle of the full configuration takes minutes of CPU time
+@pytest.mark.timeout(300)
 def test_c1_r64_full_configuration_on_the_matrix_cores():
     # 801 x 301, 16 shots batched in one launch, order 8, nt = 2401, r = 64
     # Rademacher under the default option: the accumulation and the fold run on

@@ -446,6 +446,8 @@ def test_2d_dense_off_grid_receivers():
     assert rel_l2(to_np(g_g), g_o) <= TOL
 
 
+# the FP64 oracle of the full configuration takes minutes of CPU time
+@pytest.mark.timeout(300)
 def test_c1_full_configuration():
     # 801 x 301, 16 shots batched in one launch, order 8, nt = 2401, r = 16
     # Rademacher (the benchmarked launch configuration), against the oracle
