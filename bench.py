@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--fused-3d", type=int, default=None, choices=[0, 1],
                     help="two leapfrog steps per 3D launch (library option; default: the library's)")
     ap.add_argument("--steps-2d", type=int, default=None, choices=[2, 3],
-                    help="most leapfrog steps per 2D launch (default: the library's, 2)")
+                    help="most leapfrog steps per 2D launch (default: the library's, 3)")
     return ap.parse_args()
 
 

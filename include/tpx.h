@@ -251,8 +251,8 @@ enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2, TPX_OPT_FUSED
 /* TPX_OPT_FUSED_STEPS_3D (default 0): 3D launches advance two leapfrog steps
  * at a time (as 2D launches always do) instead of one.  Results are bitwise
  * the same either way; only speed differs. */
-/* TPX_OPT_STEPS_2D (default 2): the most leapfrog steps one 2D launch
- * advances, 2 or 3.  Three-step launches (temporal blocking over three levels:
+/* TPX_OPT_STEPS_2D (default 3): the most leapfrog steps one 2D launch
+ * advances, 3 or 2.  Three-step launches (temporal blocking over three levels:
  * u^{k-1}, u^k and beta read once, three new levels written) are used on
  * problems with the default tile height; they need their own injection tables
  * and a plain forward/adjoint ring of six levels instead of four, so the option

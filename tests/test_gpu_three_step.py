@@ -1,4 +1,4 @@
-"""GPU: three leapfrog steps per 2D launch (TPX_OPT_STEPS_2D = 3; default 2).
+"""GPU: three leapfrog steps per 2D launch (TPX_OPT_STEPS_2D = 3, the default).
 
 The three-step kernel computes u^{k+1} on its tile plus a 2R halo, u^{k+2} on
 the tile plus an R halo and u^{k+3} on the tile, each node with the one-step
@@ -29,9 +29,10 @@ TOL = 1e-4
 @pytest.fixture(autouse=True)
 def three_steps():
     ensure_built()
+    old = tpx.get_option(tpx.OPT_STEPS_2D)
     tpx.set_option(tpx.OPT_STEPS_2D, 3)
     yield
-    tpx.set_option(tpx.OPT_STEPS_2D, 2)
+    tpx.set_option(tpx.OPT_STEPS_2D, old)
 
 
 def _case(order=8, nt=90, edge_sources=False, smooth_sigma=3.0):
