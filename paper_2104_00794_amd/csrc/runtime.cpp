@@ -911,6 +911,16 @@ int max_steps_per_launch(const Ctx &C, int ring_slots_used) {
     return C.P.three && ring_slots_used >= 6 ? 3 : 2;
 }
 
+// Steps of the next launch: at most `most`, and `left` remain in the current
+// segment (the record, the caller's budget, the contraction block).  Four
+// left under three-step launches go as two and two: a three-step launch and a
+// one-step one cost more than two two-step ones.
+int steps_for_launch(int most, int64_t left) {
+    int n = (int)std::max<int64_t>(std::min<int64_t>(most, left), 1);
+    if (n == 3 && left == 4) n = 2;
+    return n;
+}
+
 tpx_status fwd_begin(Ctx &C, FwdLoop &f, const float *wavelet, float *d, float *hist, const float *Z, int r,
                      float *ubar, int dtt = 0) {
     const Layout &L = C.P.L;
@@ -962,9 +972,9 @@ tpx_status fwd_advance(Ctx &C, FwdLoop &f, int64_t max_steps, int64_t *used) {
         const bool ovl = f.Z && C.plan.overlap;
         // steps in this launch: within the record, the caller's budget and
         // (with contractions) the current block
-        int64_t lim = std::min<int64_t>(max_steps_per_launch(C, f.ns), std::min<int64_t>(nt - 1 - k, max_steps - n));
-        if (f.Z) lim = std::min<int64_t>(lim, C.plan.block - (s - f.s_lo));
-        const int nstep = (int)std::max<int64_t>(lim, 1);
+        int64_t left = std::min<int64_t>(nt - 1 - k, max_steps - n);
+        if (f.Z) left = std::min<int64_t>(left, C.plan.block - (s - f.s_lo));
+        const int nstep = steps_for_launch(max_steps_per_launch(C, f.ns), left);
         if (ovl && s == f.s_lo) {
             tpx_status st = overlap_guard(C, f.blk);
             if (st != TPX_OK) return st;
@@ -1114,9 +1124,9 @@ tpx_status adj_advance(Ctx &C, AdjLoop &b, int64_t max_steps, int64_t *used) {
         const bool ovl = accum && C.plan.overlap;
         // steps in this launch: down to k = 1, within the caller's budget and
         // (with contractions) the current block
-        int64_t lim = std::min<int64_t>(max_steps_per_launch(C, ns), std::min<int64_t>(k, max_steps - n));
-        if (accum) lim = std::min<int64_t>(lim, C.plan.block - (b.s_hi - k));
-        const int nstep = (int)std::max<int64_t>(lim, 1);
+        int64_t left = std::min<int64_t>(k, max_steps - n);
+        if (accum) left = std::min<int64_t>(left, C.plan.block - (b.s_hi - k));
+        const int nstep = steps_for_launch(max_steps_per_launch(C, ns), left);
         if (ovl && k == b.s_hi) {
             tpx_status st = overlap_guard(C, b.blk);
             if (st != TPX_OK) return st;

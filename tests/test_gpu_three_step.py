@@ -168,3 +168,32 @@ def test_three_steps_with_overlapped_contractions(block):
     torch.cuda.synchronize()
     assert torch.equal(g3, g3o) and torch.equal(J3, J3o)
     assert torch.equal(g3, g2) and torch.equal(J3, J2)
+
+
+def test_four_remaining_steps_go_as_two_and_two():
+    # contraction blocks of 7 steps: 3 + 2 + 2 (not 3 + 3 + 1); the last block
+    # of each pass is 5 steps, 3 + 2.  A probed gradient then makes no one-step
+    # launch, and its result is bitwise that of two-step launches.
+    import torch
+    print("[three_step] block remainders", flush=True)
+    c = _case(order=8, nt=90)
+    dobs = c.dobs_oracle()
+    tg, geom, m, d = c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs)
+    probe = tpx.Probe(r=8, seed=3, block=7)
+    tpx.profile_enable(True)
+    try:
+        g3, J3 = tpx.gradient_probed(tg, geom, probe, m, d)
+        torch.cuda.synchronize()
+        counts = [tpx.profile_read(k)[1] for k in (tpx.KERNEL_STEP3, tpx.KERNEL_STEP2, tpx.KERNEL_STEP)]
+    finally:
+        tpx.profile_enable(False)
+    # 89 steps per pass: twelve blocks of 7 (one three-step and two two-step
+    # launches each) and one of 5 (one of each)
+    assert counts == [26, 50, 0], counts
+    tpx.set_option(tpx.OPT_STEPS_2D, 2)
+    try:
+        g2, J2 = tpx.gradient_probed(tg, geom, probe, m, d)
+    finally:
+        tpx.set_option(tpx.OPT_STEPS_2D, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(g3, g2) and torch.equal(J3, J2)
