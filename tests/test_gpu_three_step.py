@@ -197,3 +197,26 @@ def test_four_remaining_steps_go_as_two_and_two():
         tpx.set_option(tpx.OPT_STEPS_2D, 3)
     torch.cuda.synchronize()
     assert torch.equal(g3, g2) and torch.equal(J3, J2)
+
+
+def test_split_pair_and_chunked_job_match_the_gradient_call():
+    # the split forward/backward pair (the autograd path) and a job advanced in
+    # 64-step chunks (the serving path: 20 three-step launches and 2 + 2) give
+    # the gradient call's traces, g and J bit for bit under three-step launches
+    # (11-step blocks: 3 + 3 + 3 + 2)
+    import torch
+    print("[three_step] split pair and chunked job", flush=True)
+    c = _case(order=8, nt=150)
+    dobs = c.dobs_oracle()
+    tg, geom, m, d = c.tgrid(), c.tgeom(), cuda(c.m0), cuda(dobs)
+    probe = tpx.Probe(r=8, seed=5, block=11)
+    g, J, d_pred = tpx.gradient_probed(tg, geom, probe, m, d, return_traces=True)
+    dsp, state = tpx.forward_probed(tg, geom, probe, m)
+    g_split = tpx.backward_probed(tg, geom, probe, m, dsp - d, state)
+    job = tpx.Job(tg, geom, probe, m, d)
+    while not job.advance(64):
+        pass
+    torch.cuda.synchronize()
+    assert torch.equal(dsp, d_pred)
+    assert torch.equal(g_split, g)
+    assert torch.equal(job.g, g) and torch.equal(job.J, J)
