@@ -253,11 +253,10 @@ enum { TPX_OPT_OVERLAP_CONTRACTIONS = 1, TPX_OPT_MATRIX_CORES = 2, TPX_OPT_FUSED
  * the same either way; only speed differs. */
 /* TPX_OPT_STEPS_2D (default 3): the most leapfrog steps one 2D launch
  * advances, 3 or 2.  Three-step launches (temporal blocking over three levels:
- * u^{k-1}, u^k and beta read once, three new levels written) are used on
- * problems with the default tile height; they need their own injection tables
- * and a plain forward/adjoint ring of six levels instead of four, so the option
- * changes workspace sizes: set it before sizing a workspace.  Results are
- * bitwise the same for any setting. */
+ * u^{k-1}, u^k and beta read once, three new levels written) need their own
+ * injection tables and a plain forward/adjoint ring of six levels instead of
+ * four, so the option changes workspace sizes: set it before sizing a
+ * workspace.  Results are bitwise the same for any setting. */
 /* TPX_OPT_MATRIX_CORES (default 1): the probe contractions of the time
  * blocks are dense products (r x b by b x points) and can run on the matrix
  * cores when r is a multiple of 16: bfloat16 MFMA with each FP32 field value

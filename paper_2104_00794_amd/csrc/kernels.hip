@@ -1194,10 +1194,13 @@ hipError_t launch_step(const Layout &L, const Physics &ph, const StepArgs &a, hi
         else hipLaunchKernelGGL((k_step2d<RR, NS, T2Z_SMALL>), grid, dim3(256), 0, stream, L, ph, a); \
     } while (0)
         if (a.nstep == 3) {
-            // L is the three-step layout: tiles of t3x(R) columns and T2Z rows
-            if (tz != T2Z || L.tile[0] != t3x(L.R)) return hipErrorInvalidValue;
-            if (L.R == 2) hipLaunchKernelGGL((k_step2d3<2, T2Z>), grid, dim3(256), 0, stream, L, ph, a);
-            else hipLaunchKernelGGL((k_step2d3<4, T2Z>), grid, dim3(256), 0, stream, L, ph, a);
+            // L is the three-step layout: tiles of t3x(R) columns, rows as the two-step tiles
+            if (L.tile[0] != t3x(L.R)) return hipErrorInvalidValue;
+#define TPX_STEP2D3(RR, TT) hipLaunchKernelGGL((k_step2d3<RR, TT>), grid, dim3(256), 0, stream, L, ph, a)
+            if (tz == T2Z) { if (L.R == 2) TPX_STEP2D3(2, T2Z); else TPX_STEP2D3(4, T2Z); }
+            else if (tz == T2Z_MID) { if (L.R == 2) TPX_STEP2D3(2, T2Z_MID); else TPX_STEP2D3(4, T2Z_MID); }
+            else { if (L.R == 2) TPX_STEP2D3(2, T2Z_SMALL); else TPX_STEP2D3(4, T2Z_SMALL); }
+#undef TPX_STEP2D3
         } else if (a.nstep == 2) {
             if (L.R == 2) TPX_STEP2D(2, 2);
             else TPX_STEP2D(4, 2);

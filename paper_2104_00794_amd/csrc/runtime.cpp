@@ -127,9 +127,10 @@ void stencil_weights(int order, double c[5]) {
     }
 }
 
-// Most leapfrog steps one 2D launch advances: 3 (default) or 2.  Three-step
-// launches are used with the default tile height only; on the 16-shot
-// 801 x 301 gradient they take 11.3 us per step against 11.7 for two-step ones.
+// Most leapfrog steps one 2D launch advances: 3 (default) or 2.  On the
+// 16-shot 801 x 301 gradient three-step launches take 11.3 us per step against
+// 11.7 for two-step ones; on small problems, bound by each launch's latency,
+// a third of the launches go.
 std::atomic<int> g_steps2d{3};
 
 struct Problem {
@@ -207,13 +208,13 @@ tpx_status make_problem(const tpx_grid *g, const tpx_geom *geo, Problem *P) {
     L.tiles_per_shot = L.ntiles[0] * L.ntiles[1] * L.ntiles[2];
     L.tz3 = 0;
     P->three = false;
-    if (L.ndim == 2 && L.tile[2] == T2Z && g_steps2d.load() >= 3) {
-        // three-step tiles: t3x(R) columns, maps over the first step's region
-        // (the tile plus 2R on every side)
+    if (L.ndim == 2 && g_steps2d.load() >= 3) {
+        // three-step tiles: t3x(R) columns and the two-step tiles' height, maps
+        // over the first step's region (the tile plus 2R on every side)
         Layout &L3 = P->L3;
         L3 = L;
         L3.tile[0] = t3x(L.R);
-        L3.map[2] = T2Z + 4 * L.R;
+        L3.map[2] = (int)L.tile[2] + 4 * L.R;
         L3.map_org[0] = -2 * L.R;
         L3.map_org[2] = -2 * L.R;
         for (int a = 0; a < 3; ++a) L3.ntiles[a] = (L3.P[a] + L3.tile[a] - 1) / L3.tile[a];

@@ -36,7 +36,7 @@ constexpr int T2Z = 32;
 constexpr int T2Z_MID = 16;
 constexpr int T2Z_SMALL = 8;
 __host__ __device__ constexpr int t2x(int R) { return 64 - 2 * R; }
-// Three-step 2D kernel: T2Z rows by 64 - 4R columns; lane l holds column
+// Three-step 2D kernel: the two-step tiles' height by 64 - 4R columns; lane l holds column
 // x0 - 2R + l, so a wave row covers the tile plus a 2R-wide halo (the region
 // of the first of its three steps).
 __host__ __device__ constexpr int t3x(int R) { return 64 - 4 * R; }

@@ -220,3 +220,29 @@ def test_split_pair_and_chunked_job_match_the_gradient_call():
     assert torch.equal(dsp, d_pred)
     assert torch.equal(g_split, g)
     assert torch.equal(job.g, g) and torch.equal(job.J, J)
+
+
+@pytest.mark.parametrize("nx,nz,shots,tile", [(140, 60, 4, 8), (300, 120, 14, 16)])
+def test_three_steps_on_short_tiles(nx, nz, shots, tile):
+    # small problems take 8- or 16-row tiles; their three-step launches use the
+    # same tile height: traces, the adjoint, the probed and the full-storage
+    # gradient are bitwise those of two-step launches (the oracle parity of
+    # small problems is checked by the parity tests, which run three-step
+    # launches by default)
+    import torch
+    print(f"[three_step] short tiles {nx}x{nz} shots={shots}", flush=True)
+    wl = small_2d(nz=nz, nx=nx, nt=120, nbl=10, nshots=shots, nrec=11, seed=17)
+    c = Case(wl.with_(smooth_sigma=15.0))
+    dobs = c.dobs_oracle()
+    probe = tpx.Probe(r=8, seed=2, block=10)
+    n3 = _uses_three_steps(c)
+    assert n3[0] > 0 and n3[2] == 0, n3
+    three = _run_all(c, dobs, probe)
+    try:
+        tpx.set_option(tpx.OPT_STEPS_2D, 2)
+        assert _uses_three_steps(c)[0] == 0
+        two = _run_all(c, dobs, probe)
+    finally:
+        tpx.set_option(tpx.OPT_STEPS_2D, 3)
+    for k in three:
+        assert np.array_equal(three[k], two[k]), k
