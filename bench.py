@@ -62,8 +62,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=60, help="requests in the serving trace")
     ap.add_argument("--budget-gb", type=float, default=200.0, help="HBM budget of the server")
     ap.add_argument("--chunk-steps", type=int, default=64, help="time steps a served job advances per turn")
-    ap.add_argument("--max-active", type=int, default=4,
-                    help="jobs the server keeps on the GPU at once (default: one per hardware queue)")
+    ap.add_argument("--max-active", type=int, default=3,
+                    help="jobs the server keeps on the GPU at once (default: one fewer than the hardware queues)")
     ap.add_argument("--inflight", type=int, default=2, help="chunks each served job keeps queued")
     ap.add_argument("--large-points", type=float, default=3e6,
                     help="padded points over a job's shots from which it counts as large")
